@@ -1,0 +1,453 @@
+/*
+ * dg_oracle.c -- plain, serial FP64 CPU reference of the modal DG method.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this code.  It shares no code with
+ * the HIP library: basis, geometry, flux, numerical flux and time stepping
+ * are written out here again from their definitions.
+ *
+ * What it computes (Fuhry, Giuliani, Krivodonova, "Discontinuous Galerkin
+ * methods on graphics processing units for nonlinear hyperbolic conservation
+ * laws"):
+ *   - the semi-discrete right-hand side of eq. (2ddg0): for every element i,
+ *     mode j and equation m
+ *       R = (1/det J_i) [ sum_k w_k grad_r phi_j(r_k) . (adj(J_i) F(U_i(r_k)))
+ *                         - sum_q l_q sum_k omega_k phi_j(r_qk) Fn_k ]
+ *     with the volume term of eq. (volume) after the element map eq. (2dmap)
+ *     and the surface term eq. (surface) after the edge map eq. (1dmap);
+ *   - the element loop visits one element at a time and evaluates the
+ *     numerical flux of each of its three sides itself, so every interior
+ *     edge flux is computed twice (once from each side);
+ *   - the neighbour's trace is taken at the reversed edge point (Section
+ *     "Surface Integration Kernel": the two elements traverse a shared edge
+ *     in opposite directions);
+ *   - L2 projection onto the orthonormal basis (mass matrix = det J * I);
+ *   - three-stage SSP Runge-Kutta in Shu-Osher form and a CFL time step.
+ *
+ * Conventions (readings of points the paper leaves open):
+ *   - J = d(x,y)/d(r,s) = [[x2-x1, x3-x1], [y2-y1, y3-y1]];
+ *     grad_x phi = J^{-T} grad_r phi, so the volume integrand is
+ *     grad_r phi . (adj(J) F) with adj(J) = det(J) J^{-1}.
+ *   - Basis: orthonormal Dubiner polynomials on {(0,0),(1,0),(0,1)}:
+ *       phi_ab = sqrt(2(2a+1)(a+b+1)) g_a(r,s) P_b^{(2a+1,0)}(2s-1),
+ *       g_a = (1-s)^a P_a(2r/(1-s)-1) = sum_i C(a,i)^2 (r+s-1)^i r^(a-i),
+ *     ordered by total degree a+b, then by b.
+ *   - Local side q runs from vertex q to vertex q+1 (counter-clockwise);
+ *     side points: q=0 ((1+x)/2, 0), q=1 ((1-x)/2, (1+x)/2), q=2 (0, (1-x)/2)
+ *     for Gauss node x in [-1,1]; the neighbour's point for node k is p-k.
+ *   - Numerical flux: local Lax-Friedrichs,
+ *       Fn = (F(U_L).n + F(U_R).n)/2 - lambda (U_R - U_L)/2,
+ *       lambda = max(|v_L.n| + c_L, |v_R.n| + c_R),  c = sqrt(gamma p / rho).
+ *   - Edge scale l = |edge|/2 (eq. (len)); Gauss weights sum to 2.
+ *   - Time step: dt = CFL min_i r_i / (|v_i| + c_i) with the inscribed radius
+ *     r_i = det J_i / perimeter_i and the state at the cell average
+ *     sqrt(2) c_{i,0}.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define M 4
+#define NP_MAX 21
+#define NQ_MAX 25
+#define NE_MAX 6
+
+typedef struct {
+    int p, np, nq, ne;
+    int64_t n;
+    double gamma;
+    double *vxy;     /* [n][3][2] */
+    int64_t *nbr;    /* [n][3] */
+    int8_t *nbs;     /* [n][3] */
+    double *qr, *qs, *qw; /* volume rule [nq] */
+    double *gx, *gw;      /* Gauss-Legendre [ne] */
+    /* basis values at the fixed reference points */
+    double *phi_v; /* [nq][np] */
+    double *dr_v;  /* [nq][np] */
+    double *ds_v;  /* [nq][np] */
+    double *phi_s; /* [3][ne][np] */
+} orc_ctx;
+
+/* ---------------------------------------------------------------- basis */
+static double binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+static double ipow(double x, int e)
+{
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+/* Jacobi polynomial by its explicit sum:
+ * P_n^{(a,b)}(x) = sum_s C(n+a, n-s) C(n+b, s) ((x-1)/2)^s ((x+1)/2)^(n-s) */
+static double jacobi(int n, int a, int b, double x)
+{
+    double xm = 0.5 * (x - 1.0), xp = 0.5 * (x + 1.0), sum = 0.0;
+    for (int s = 0; s <= n; ++s) sum += binom(n + a, n - s) * binom(n + b, s) * ipow(xm, s) * ipow(xp, n - s);
+    return sum;
+}
+
+/* d/dx P_n^{(a,b)}(x) = (n+a+b+1)/2 P_{n-1}^{(a+1,b+1)}(x) */
+static double djacobi(int n, int a, int b, double x)
+{
+    if (n == 0) return 0.0;
+    return 0.5 * (double)(n + a + b + 1) * jacobi(n - 1, a + 1, b + 1, x);
+}
+
+/* All np basis functions and their r, s derivatives at (r, s). */
+void orc_basis(int p, double r, double s, double *phi, double *dphidr, double *dphids)
+{
+    int j = 0;
+    double t = r + s - 1.0;
+    for (int d = 0; d <= p; ++d) {
+        for (int b = 0; b <= d; ++b, ++j) {
+            int a = d - b;
+            double g = 0.0, gr = 0.0, gs = 0.0;
+            for (int i = 0; i <= a; ++i) {
+                double c2 = binom(a, i) * binom(a, i);
+                g += c2 * ipow(t, i) * ipow(r, a - i);
+                if (i >= 1) {
+                    gr += c2 * (double)i * ipow(t, i - 1) * ipow(r, a - i);
+                    gs += c2 * (double)i * ipow(t, i - 1) * ipow(r, a - i);
+                }
+                if (a - i >= 1) gr += c2 * (double)(a - i) * ipow(t, i) * ipow(r, a - i - 1);
+            }
+            double h = jacobi(b, 2 * a + 1, 0, 2.0 * s - 1.0);
+            double hs = 2.0 * djacobi(b, 2 * a + 1, 0, 2.0 * s - 1.0);
+            double K = sqrt(2.0 * (2 * a + 1) * (a + b + 1));
+            if (phi) phi[j] = K * g * h;
+            if (dphidr) dphidr[j] = K * gr * h;
+            if (dphids) dphids[j] = K * (gs * h + g * hs);
+        }
+    }
+}
+
+static void side_point(int q, double x, double *r, double *s)
+{
+    if (q == 0) {
+        *r = 0.5 * (1.0 + x);
+        *s = 0.0;
+    } else if (q == 1) {
+        *r = 0.5 * (1.0 - x);
+        *s = 0.5 * (1.0 + x);
+    } else {
+        *r = 0.0;
+        *s = 0.5 * (1.0 - x);
+    }
+}
+
+/* -------------------------------------------------------------- context */
+orc_ctx *orc_create(int p, int64_t n, const double *vxy, const int64_t *nbr, const int8_t *nbs, double gamma, int nq,
+                    const double *qr, const double *qs, const double *qw, int ne, const double *gx, const double *gw)
+{
+    if (p < 1 || p > 5 || nq > NQ_MAX || ne > NE_MAX) return NULL;
+    orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+    c->p = p;
+    c->np = (p + 1) * (p + 2) / 2;
+    c->nq = nq;
+    c->ne = ne;
+    c->n = n;
+    c->gamma = gamma;
+    c->vxy = (double *)malloc(sizeof(double) * 6 * n);
+    memcpy(c->vxy, vxy, sizeof(double) * 6 * n);
+    c->nbr = (int64_t *)malloc(sizeof(int64_t) * 3 * n);
+    memcpy(c->nbr, nbr, sizeof(int64_t) * 3 * n);
+    c->nbs = (int8_t *)malloc(3 * n);
+    memcpy(c->nbs, nbs, 3 * n);
+    c->qr = (double *)malloc(sizeof(double) * nq);
+    c->qs = (double *)malloc(sizeof(double) * nq);
+    c->qw = (double *)malloc(sizeof(double) * nq);
+    memcpy(c->qr, qr, sizeof(double) * nq);
+    memcpy(c->qs, qs, sizeof(double) * nq);
+    memcpy(c->qw, qw, sizeof(double) * nq);
+    c->gx = (double *)malloc(sizeof(double) * ne);
+    c->gw = (double *)malloc(sizeof(double) * ne);
+    memcpy(c->gx, gx, sizeof(double) * ne);
+    memcpy(c->gw, gw, sizeof(double) * ne);
+    int np = c->np;
+    c->phi_v = (double *)malloc(sizeof(double) * nq * np);
+    c->dr_v = (double *)malloc(sizeof(double) * nq * np);
+    c->ds_v = (double *)malloc(sizeof(double) * nq * np);
+    c->phi_s = (double *)malloc(sizeof(double) * 3 * ne * np);
+    for (int k = 0; k < nq; ++k) orc_basis(p, qr[k], qs[k], c->phi_v + k * np, c->dr_v + k * np, c->ds_v + k * np);
+    for (int q = 0; q < 3; ++q)
+        for (int k = 0; k < ne; ++k) {
+            double r, s;
+            side_point(q, gx[k], &r, &s);
+            orc_basis(p, r, s, c->phi_s + (q * ne + k) * np, NULL, NULL);
+        }
+    return c;
+}
+
+void orc_destroy(orc_ctx *c)
+{
+    if (!c) return;
+    free(c->vxy);
+    free(c->nbr);
+    free(c->nbs);
+    free(c->qr);
+    free(c->qs);
+    free(c->qw);
+    free(c->gx);
+    free(c->gw);
+    free(c->phi_v);
+    free(c->dr_v);
+    free(c->ds_v);
+    free(c->phi_s);
+    free(c);
+}
+
+int orc_np(const orc_ctx *c) { return c->np; }
+
+/* ------------------------------------------------------------- geometry */
+static void element_geometry(const orc_ctx *c, int64_t i, double adj[2][2], double *det)
+{
+    const double *v = c->vxy + 6 * i;
+    double x1 = v[0], y1 = v[1], x2 = v[2], y2 = v[3], x3 = v[4], y3 = v[5];
+    *det = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
+    adj[0][0] = y3 - y1;
+    adj[0][1] = -(x3 - x1);
+    adj[1][0] = -(y2 - y1);
+    adj[1][1] = x2 - x1;
+}
+
+/* outward unit normal and half length of local side q (vertex q -> q+1) */
+static void side_geometry(const orc_ctx *c, int64_t i, int q, double *nx, double *ny, double *l)
+{
+    const double *v = c->vxy + 6 * i;
+    int a = q, b = (q + 1) % 3;
+    double dx = v[2 * b] - v[2 * a], dy = v[2 * b + 1] - v[2 * a + 1];
+    double len = sqrt(dx * dx + dy * dy);
+    *nx = dy / len;
+    *ny = -dx / len;
+    *l = 0.5 * len;
+}
+
+void orc_det(const orc_ctx *c, double *det)
+{
+    for (int64_t i = 0; i < c->n; ++i) {
+        double adj[2][2];
+        element_geometry(c, i, adj, det + i);
+    }
+}
+
+/* physical coordinates of reference points (r, s) on every element */
+void orc_map_points(const orc_ctx *c, int npts, const double *r, const double *s, double *xy /* [n][npts][2] */)
+{
+    for (int64_t i = 0; i < c->n; ++i) {
+        const double *v = c->vxy + 6 * i;
+        for (int k = 0; k < npts; ++k) {
+            double l1 = 1.0 - r[k] - s[k];
+            xy[(i * npts + k) * 2 + 0] = v[0] * l1 + v[2] * r[k] + v[4] * s[k];
+            xy[(i * npts + k) * 2 + 1] = v[1] * l1 + v[3] * r[k] + v[5] * s[k];
+        }
+    }
+}
+
+void orc_quad_points(const orc_ctx *c, double *xy) { orc_map_points(c, c->nq, c->qr, c->qs, xy); }
+
+/* U_h at reference points of every element: out[n][npts][M] */
+void orc_eval(const orc_ctx *c, const double *C, int npts, const double *r, const double *s, double *out)
+{
+    int np = c->np;
+    double *phi = (double *)malloc(sizeof(double) * npts * np);
+    for (int k = 0; k < npts; ++k) orc_basis(c->p, r[k], s[k], phi + k * np, NULL, NULL);
+    for (int64_t i = 0; i < c->n; ++i)
+        for (int k = 0; k < npts; ++k)
+            for (int m = 0; m < M; ++m) {
+                double u = 0.0;
+                for (int j = 0; j < np; ++j) u += C[(i * M + m) * np + j] * phi[k * np + j];
+                out[(i * npts + k) * M + m] = u;
+            }
+    free(phi);
+}
+
+/* ------------------------------------------------------------ physics */
+/* Euler flux, eq. (euler), with p = (gamma-1)(E - rho |v|^2 / 2) */
+static void euler_flux(double gamma, const double U[M], double Fx[M], double Fy[M])
+{
+    double rho = U[0], u = U[1] / rho, v = U[2] / rho, E = U[3];
+    double pr = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+    Fx[0] = rho * u;
+    Fx[1] = rho * u * u + pr;
+    Fx[2] = rho * u * v;
+    Fx[3] = u * (E + pr);
+    Fy[0] = rho * v;
+    Fy[1] = rho * u * v;
+    Fy[2] = rho * v * v + pr;
+    Fy[3] = v * (E + pr);
+}
+
+static void llf(double gamma, const double UL[M], const double UR[M], double nx, double ny, double Fn[M])
+{
+    double FxL[M], FyL[M], FxR[M], FyR[M];
+    euler_flux(gamma, UL, FxL, FyL);
+    euler_flux(gamma, UR, FxR, FyR);
+    double vnL = (UL[1] / UL[0]) * nx + (UL[2] / UL[0]) * ny;
+    double vnR = (UR[1] / UR[0]) * nx + (UR[2] / UR[0]) * ny;
+    double pL = (gamma - 1.0) * (UL[3] - 0.5 * UL[0] * ((UL[1] / UL[0]) * (UL[1] / UL[0]) + (UL[2] / UL[0]) * (UL[2] / UL[0])));
+    double pR = (gamma - 1.0) * (UR[3] - 0.5 * UR[0] * ((UR[1] / UR[0]) * (UR[1] / UR[0]) + (UR[2] / UR[0]) * (UR[2] / UR[0])));
+    double lamL = fabs(vnL) + sqrt(gamma * pL / UL[0]);
+    double lamR = fabs(vnR) + sqrt(gamma * pR / UR[0]);
+    double lam = lamL >= lamR ? lamL : lamR;
+    for (int m = 0; m < M; ++m) {
+        double fL = FxL[m] * nx + FyL[m] * ny;
+        double fR = FxR[m] * nx + FyR[m] * ny;
+        Fn[m] = 0.5 * (fL + fR) - 0.5 * lam * (UR[m] - UL[m]);
+    }
+}
+
+/* ------------------------------------------------------------------ RHS */
+static void rhs_element(const orc_ctx *c, const double *C, double *R, int64_t i)
+{
+    const int np = c->np, nq = c->nq, ne = c->ne;
+    double adj[2][2], det;
+    element_geometry(c, i, adj, &det);
+    const double *ci = C + i * M * np;
+    double vol[M][NP_MAX], sur[M][NP_MAX];
+    memset(vol, 0, sizeof(vol));
+    memset(sur, 0, sizeof(sur));
+
+    /* volume integral, eq. (volume) */
+    for (int k = 0; k < nq; ++k) {
+        double U[M], Fx[M], Fy[M];
+        for (int m = 0; m < M; ++m) {
+            U[m] = 0.0;
+            for (int j = 0; j < np; ++j) U[m] += ci[m * np + j] * c->phi_v[k * np + j];
+        }
+        euler_flux(c->gamma, U, Fx, Fy);
+        for (int m = 0; m < M; ++m) {
+            double Gr = adj[0][0] * Fx[m] + adj[0][1] * Fy[m];
+            double Gs = adj[1][0] * Fx[m] + adj[1][1] * Fy[m];
+            for (int j = 0; j < np; ++j)
+                vol[m][j] += c->qw[k] * (c->dr_v[k * np + j] * Gr + c->ds_v[k * np + j] * Gs);
+        }
+    }
+
+    /* surface integral, eq. (surface): the three sides of this element */
+    for (int q = 0; q < 3; ++q) {
+        int64_t nb = c->nbr[i * 3 + q];
+        int qn = c->nbs[i * 3 + q];
+        const double *cn = C + nb * M * np;
+        double nx, ny, l;
+        side_geometry(c, i, q, &nx, &ny, &l);
+        for (int k = 0; k < ne; ++k) {
+            const double *phiL = c->phi_s + (q * ne + k) * np;
+            const double *phiR = c->phi_s + (qn * ne + (ne - 1 - k)) * np;
+            double UL[M], UR[M], Fn[M];
+            for (int m = 0; m < M; ++m) {
+                UL[m] = 0.0;
+                UR[m] = 0.0;
+                for (int j = 0; j < np; ++j) {
+                    UL[m] += ci[m * np + j] * phiL[j];
+                    UR[m] += cn[m * np + j] * phiR[j];
+                }
+            }
+            llf(c->gamma, UL, UR, nx, ny, Fn);
+            for (int m = 0; m < M; ++m)
+                for (int j = 0; j < np; ++j) sur[m][j] += l * c->gw[k] * phiL[j] * Fn[m];
+        }
+    }
+
+    /* eq. (2ddg0): orthonormal basis, so the inverse mass matrix is 1/det J */
+    for (int m = 0; m < M; ++m)
+        for (int j = 0; j < np; ++j) R[(i * M + m) * np + j] = (vol[m][j] - sur[m][j]) / det;
+}
+
+/* R = L(C), user layout [n][M][np] */
+void orc_rhs(const orc_ctx *c, const double *C, double *R)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < c->n; ++i) rhs_element(c, C, R, i);
+}
+
+/* L2 projection of point values u[n][nq][M] at the volume points:
+ * c_j = sum_k w_k phi_j(r_k) u(x(r_k))  (mass matrix det J * I) */
+void orc_project(const orc_ctx *c, const double *u, double *C)
+{
+    const int np = c->np, nq = c->nq;
+    for (int64_t i = 0; i < c->n; ++i)
+        for (int m = 0; m < M; ++m)
+            for (int j = 0; j < np; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < nq; ++k) s += c->qw[k] * c->phi_v[k * np + j] * u[(i * nq + k) * M + m];
+                C[(i * M + m) * np + j] = s;
+            }
+}
+
+/* CFL time step; returns 0, or -1 (and dt = NaN) for a non-physical mean */
+int orc_max_dt(const orc_ctx *c, const double *C, double cfl, double *dt)
+{
+    const int np = c->np;
+    double best = INFINITY;
+    int bad = 0;
+    for (int64_t i = 0; i < c->n; ++i) {
+        double adj[2][2], det;
+        element_geometry(c, i, adj, &det);
+        double per = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            double nx, ny, l;
+            side_geometry(c, i, q, &nx, &ny, &l);
+            per += 2.0 * l;
+        }
+        double U[M];
+        for (int m = 0; m < M; ++m) U[m] = sqrt(2.0) * C[(i * M + m) * np + 0];
+        double rho = U[0], u = U[1] / rho, v = U[2] / rho;
+        double pr = (c->gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v));
+        if (!(rho > 0.0) || !(pr > 0.0)) {
+            bad = 1;
+            continue;
+        }
+        double lam = sqrt(u * u + v * v) + sqrt(c->gamma * pr / rho);
+        double d = (det / per) / lam;
+        if (d < best) best = d;
+    }
+    if (bad) {
+        *dt = NAN;
+        return -1;
+    }
+    *dt = cfl * best;
+    return 0;
+}
+
+/* One SSP-RK3 step in Shu-Osher form, in place:
+ *   u1 = u + dt L(u)
+ *   u2 = 3/4 u + 1/4 (u1 + dt L(u1))
+ *   u  = 1/3 u + 2/3 (u2 + dt L(u2)) */
+void orc_rk3_step(const orc_ctx *c, double *C, double dt)
+{
+    size_t len = (size_t)c->n * M * c->np;
+    double *L = (double *)malloc(sizeof(double) * len);
+    double *u1 = (double *)malloc(sizeof(double) * len);
+    double *u2 = (double *)malloc(sizeof(double) * len);
+    orc_rhs(c, C, L);
+    for (size_t x = 0; x < len; ++x) u1[x] = C[x] + dt * L[x];
+    orc_rhs(c, u1, L);
+    for (size_t x = 0; x < len; ++x) u2[x] = 0.75 * C[x] + 0.25 * (u1[x] + dt * L[x]);
+    orc_rhs(c, u2, L);
+    for (size_t x = 0; x < len; ++x) C[x] = (1.0 / 3.0) * C[x] + (2.0 / 3.0) * (u2[x] + dt * L[x]);
+    free(L);
+    free(u1);
+    free(u2);
+}
+
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

@@ -1,0 +1,168 @@
+"""Mutation check of the oracle's pins (test infrastructure, CPU only).
+
+Each case plants one plausible mistake in a copy of the oracle's C source
+(a dropped term, a wrong sign, index or transposed operand), compiles it
+with gcc and runs quick versions of the pins against it.  The unmodified
+oracle must pass every pin; every mutant must fail at least one.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import quadrature as Q
+from paper_1601_07944_amd import workloads as W
+from test_oracle_llf_golden import check_cases
+from test_oracle_operator import det_of, exact_dudt, linear_state, relabel
+
+MUTANTS = {
+    "reversed_point_not_reversed": ("(qn * ne + (ne - 1 - k))", "(qn * ne + k)"),
+    "metric_transposed": (
+        "adj[0][1] = -(x3 - x1);\n    adj[1][0] = -(y2 - y1);",
+        "adj[0][1] = -(y2 - y1);\n    adj[1][0] = -(x3 - x1);",
+    ),
+    "normal_inward": ("*nx = dy / len;\n    *ny = -dx / len;", "*nx = -dy / len;\n    *ny = dx / len;"),
+    "edge_scale_full_length": ("*l = 0.5 * len;", "*l = len;"),
+    "side1_direction": ("*r = 0.5 * (1.0 - x);\n        *s = 0.5 * (1.0 + x);", "*r = 0.5 * (1.0 + x);\n        *s = 0.5 * (1.0 - x);"),
+    "dissipation_sign": ("- 0.5 * lam * (UR[m] - UL[m])", "+ 0.5 * lam * (UR[m] - UL[m])"),
+    "pressure_no_half": (
+        "double pr = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));",
+        "double pr = (gamma - 1.0) * (E - rho * (u * u + v * v));",
+    ),
+    "sound_speed_no_gamma": ("sqrt(gamma * pL / UL[0])", "sqrt(pL / UL[0])"),
+    "wave_speed_min": ("lamL >= lamR ? lamL : lamR", "lamL >= lamR ? lamR : lamL"),
+    "rk3_stage2_weights": ("0.75 * C[x] + 0.25 * (u1[x]", "0.5 * C[x] + 0.5 * (u1[x]"),
+    "inverse_mass_area": ("(vol[m][j] - sur[m][j]) / det", "(vol[m][j] - sur[m][j]) / (0.5 * det)"),
+    "basis_normalisation": ("double K = sqrt(2.0 * (2 * a + 1) * (a + b + 1));", "double K = sqrt((2.0 * a + 1) * (a + b + 1));"),
+    "gradient_swapped": (
+        "(c->dr_v[k * np + j] * Gr + c->ds_v[k * np + j] * Gs)",
+        "(c->ds_v[k * np + j] * Gr + c->dr_v[k * np + j] * Gs)",
+    ),
+    "volume_weight_dropped": ("vol[m][j] += c->qw[k] * (", "vol[m][j] += ("),
+    "projection_weight_dropped": ("s += c->qw[k] * c->phi_v[k * np + j]", "s += c->phi_v[k * np + j]"),
+    "dt_half_perimeter": ("per += 2.0 * l;", "per += l;"),
+    "neighbour_uses_own_coeffs": ("UR[m] += cn[m * np + j] * phiR[j];", "UR[m] += ci[m * np + j] * phiR[j];"),
+    "jacobi_derivative_factor": ("return 0.5 * (double)(n + a + b + 1) * jacobi", "return (double)(n + a + b + 1) * jacobi"),
+}
+
+
+def pin_gram(lib):
+    from test_oracle_basis import product_rule
+
+    r, s, w = product_rule(7)
+    for p in (2, 5):
+        np_ = (p + 1) * (p + 2) // 2
+        phi = np.empty((r.size, np_))
+        d1 = np.empty(np_)
+        d2 = np.empty(np_)
+        for k in range(r.size):
+            lib.orc_basis(p, float(r[k]), float(s[k]), O._p(phi[k]), O._p(d1), O._p(d2))
+        if np.abs((phi * w[:, None]).T @ phi - np.eye(np_)).max() > 1e-13:
+            return False
+    return True
+
+
+def pin_projection(lib):
+    mesh = W.square_mesh(3, 1.0, 0.2, 3)
+    orc = O.Oracle(mesh, 2, lib=lib)
+    f = lambda x, y: np.stack([1 + x * y, x - y * y, 2 + x, 3 + 0 * x], axis=-1)
+    C = orc.project(f)
+    U = orc.eval(C, np.array([0.2, 0.3]), np.array([0.1, 0.4]))
+    xy = orc.map_points(np.array([0.2, 0.3]), np.array([0.1, 0.4]))
+    return np.abs(U - f(xy[..., 0], xy[..., 1])).max() < 1e-12
+
+
+def pin_free_stream(lib):
+    mesh = W.square_mesh(4, 1.0, 0.2, 11)
+    for p in (1, 3):
+        orc = O.Oracle(mesh, p, lib=lib)
+        R = orc.rhs(orc.project(W.free_stream))
+        if not np.abs(R).max() < 1e-11:
+            return False
+    return True
+
+
+def pin_conservation(lib):
+    mesh = W.delaunay_mesh(40, 12)
+    orc = O.Oracle(mesh, 2, lib=lib)
+    R = orc.rhs(W.random_state(mesh.n_elem, orc.np, seed=1))
+    terms = det_of(mesh)[:, None] * R[:, :, 0]
+    return bool(np.all(np.abs(terms.sum(0)) < 1e-13 * np.abs(terms).sum(0)))
+
+
+def pin_poly_state(lib):
+    mesh = W.square_mesh(6, 1.0, 0.2, 21)
+    orc = O.Oracle(mesh, 3, lib=lib)
+    R = orc.rhs(orc.project(linear_state))
+    cen = mesh.centroids()
+    inner = np.all((cen > 1.5 / 6) & (cen < 1 - 1.5 / 6), axis=1)
+    Rh = orc.eval(R, np.array([0.2]), np.array([0.3]))[inner]
+    xy = orc.map_points(np.array([0.2]), np.array([0.3]))[inner]
+    ex = exact_dudt(xy[..., 0], xy[..., 1])
+    return np.abs(Rh - ex).max() < 1e-11 * np.abs(ex).max()
+
+
+def pin_relabel(lib):
+    mesh = W.square_mesh(4, 10.0, 0.2, 4)
+    shift = np.random.default_rng(9).integers(0, 3, size=mesh.n_elem)
+    out = []
+    for m in (mesh, relabel(mesh, shift)):
+        orc = O.Oracle(m, 2, lib=lib)
+        C = orc.rk3_step(orc.project(W.isentropic_vortex), 0.01)
+        xy = mesh.vxy.mean(1)[:, None, :]
+        # centroid value = mode expansion at (1/3, 1/3) in any vertex numbering
+        out.append(orc.eval(C, np.array([1 / 3]), np.array([1 / 3])))
+    return np.abs(out[0] - out[1]).max() < 1e-12
+
+
+def pin_dt(lib):
+    mesh = W.square_mesh(5, 2.0, 0.0, 0)
+    orc = O.Oracle(mesh, 1, lib=lib)
+    C = orc.project(functools.partial(W.free_stream, rho=1.2, u=0.3, v=-0.4, p=0.8))
+    dt, rc = orc.max_dt(C, 0.1)
+    ref = 0.1 * 0.4 * (1 - math.sqrt(0.5)) / (0.5 + math.sqrt(1.4 * 0.8 / 1.2))
+    return rc == 0 and abs(dt - ref) < 1e-14
+
+
+def pin_rk3(lib):
+    mesh = W.square_mesh(6, 10.0, 0.1, 2)
+    orc = O.Oracle(mesh, 1, lib=lib)
+    C0 = orc.project(W.isentropic_vortex)
+    T = 0.08
+
+    def run(n):
+        C = C0.copy()
+        for _ in range(n):
+            C = orc.rk3_step(C, T / n)
+        return C
+
+    ref = run(128)
+    e = [np.abs(run(n) - ref).max() for n in (8, 16)]
+    return math.log2(e[0] / e[1]) > 2.8
+
+
+PINS = [pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
+
+
+def run_pins(lib):
+    failed = [f.__name__ for f in PINS if not f(lib)]
+    if not check_cases(lib):
+        failed.append("llf_golden")
+    return failed
+
+
+def test_unmodified_oracle_passes_quick_pins(tmp_path):
+    lib = O.load_variant(O.source(), str(tmp_path / "orig.so"))
+    assert run_pins(lib) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = O.source()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    lib = O.load_variant(src.replace(old, new), str(tmp_path / f"{name}.so"))
+    failed = run_pins(lib)
+    assert failed, f"planted mistake {name} passed every pin"
