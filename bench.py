@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the modal DG hot path on one MI355X.
+
+Workload: isentropic vortex on the periodic square [0,10]^2, 128 x 128
+squares split into 32,768 triangles (vertices jittered by up to 0.2h, seed
+1), p = 3 (10 modes, 12-point degree-6 volume rule, 4 Gauss points per
+edge), FP64.  One step is the whole hot path: the CFL time-step reduction
+on the device followed by one SSP-RK3 step (three right-hand sides, each
+traces -> edge fluxes -> element volume/lift/inverse mass/stage update).
+
+value = DOF-updates/s = N_elem * N_p * 4 variables * 3 RHS evaluations per
+step / seconds per step, with the state resident in HBM.
+
+Prints ONE JSON line.  Extra objects:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average launch time (HIP events around each launch of the
+                timed region), against the 8 TB/s HBM peak;
+  cpu_baseline  the CPU oracle (serial C, OpenMP element loop) timed on this
+                host on a bounded sample of the same workload;
+  rhs_only      dg_rhs alone, DOF-updates/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "DOF-updates/s of DG RHS at p=3, FP64 vs mixed; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_element_kernel(n_elem: int, n_modes: int, stage0_reads: float) -> float:
+    """Bytes the method itself must move in one element-kernel launch: read
+    the stage state and write the new one (2 x 8 B x 4 x N_p per element),
+    read the stage-0 state in stages 2 and 3 (stage0_reads = launches that
+    read it / launches), and read adj(J) and 1/det J (5 doubles).  Surface
+    slots and traces are implementation traffic and are not counted."""
+    per_elem = 8.0 * 4 * n_modes * (2.0 + stage0_reads) + 5 * 8.0
+    return per_elem * n_elem
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if the summary
+    in profiles/ was taken from the current kernel source."""
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        import hashlib
+
+        with open(path) as f:
+            rec = json.load(f)
+        src = os.path.join(HERE, "paper_1601_07944_amd", "csrc", "dg_kernels.h")
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        ent = rec.get(kernel)
+        if not ent or ent.get("source_sha256_16") != digest:
+            return None
+        return ent.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(mesh, p, seconds: float):
+    """Oracle SSP-RK3 steps on the same mesh and state for about `seconds`."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1601_07944_amd import workloads as W
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = O.set_threads(cores)
+    orc = O.Oracle(mesh, p)
+    C = orc.project(W.isentropic_vortex)
+    dt, _ = orc.max_dt(C, 0.3 / (2 * p + 1))
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.max_dt(C, 0.3 / (2 * p + 1))
+        C = orc.rk3_step(C, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 1000:
+            break
+    dof = mesh.n_elem * orc.np * 4
+    assert np.isfinite(C).all()
+    return {
+        "value": dof * 3 * steps / el,
+        "unit": "DOF-updates/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{steps} SSP-RK3 steps (+ CFL reduction) of the same {mesh.n_elem}-triangle p={p} vortex state, "
+        f"{el:.1f} s wall",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(
+            "bench.py measures one GPU: the path runs on a single MI355X; a multi-GPU run "
+            "(element partition + halo exchange) is not part of this build.",
+            file=sys.stderr,
+        )
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+    from paper_1601_07944_amd import workloads as W
+
+    B.load()  # raises if the HIP library is not built
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    p = 3
+    mesh = W.square_mesh(128, 10.0, 0.2, 1)
+    dm = B.DGMesh.from_mesh(mesh, p)
+    xy = dm.quad_points().cpu().numpy()
+    u = torch.from_numpy(np.ascontiguousarray(W.isentropic_vortex(xy[..., 0], xy[..., 1]))).to(dev)
+    C = dm.project(u)
+    ws = dm.workspace("step")
+    dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
+    cfl = 0.3 / (2 * p + 1)
+    dof = dm.n * dm.np * 4
+
+    def step():
+        dm.max_dt(C, cfl, dt_dev=dt_dev, to_host=False, ws=ws)
+        dm.rk_step(C, dt_dev=dt_dev, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region, with per-kernel HIP events around every launch
+    dm.timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dm.timing(False)
+    kt = dm.timing_read()
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+
+    # the same region without the per-launch events (reported beside it)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step_plain = e0.elapsed_time(e1) / args.steps
+    _, dt_host = dm.max_dt(C, cfl)
+    assert np.isfinite(dt_host) and dt_host > 0
+
+    # dg_rhs alone
+    R = dm.empty_state()
+    rws = dm.workspace("step")
+    for _ in range(5):
+        dm.rhs(C, out=R, ws=rws)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        dm.rhs(C, out=R, ws=rws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_rhs = e0.elapsed_time(e1) / args.steps
+
+    kernels = {k: {"ms_per_launch": (ms / n if n else None), "launches": n, "share": ms / max(1e-30, sum(v[0] for v in kt.values()))}
+               for k, (ms, n) in kt.items()}
+    dominant = max(kt, key=lambda k: kt[k][0])
+    el_ms, el_n = kt["element"]
+    ach = algorithmic_bytes_element_kernel(dm.n, dm.np, 2.0 / 3.0) / (el_ms / el_n * 1e-3) / 1e9
+    traffic = load_traffic("element")
+    out = {
+        "metric": METRIC,
+        "value": dof * 3 / (ms_step * 1e-3),
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "isentropic vortex, periodic [0,10]^2, 32,768 jittered triangles (0.2h, seed 1), p=3, "
+            "FP64; step = CFL reduction + SSP-RK3 step (3 RHS)",
+            "n_elem": dm.n,
+            "p": p,
+            "dof": dof,
+        },
+        "roofline": {
+            "kernel": "element (volume + lift + 1/det J + SSP-RK3 stage)",
+            "bound": "hbm",
+            "achieved": ach,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "dominant_kernel_by_time": dominant,
+        },
+        "kernels": kernels,
+        "ms_per_step_without_kernel_events": ms_step_plain,
+        "wall_s_timed_region": wall,
+        "rhs_only": {"value": dof / (ms_rhs * 1e-3), "unit": "DOF-updates/s", "ms_per_call": ms_rhs},
+        "mixed": None,
+        "adjoint_forward_ratio": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

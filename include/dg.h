@@ -1,0 +1,192 @@
+/*
+ * dg.h -- C ABI of libdgmi: the right-hand side of a modal discontinuous
+ * Galerkin discretisation of the 2D Euler equations on triangle meshes, and
+ * its SSP Runge-Kutta stepping, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Fuhry, Giuliani and Krivodonova, "Discontinuous
+ * Galerkin methods on graphics processing units for nonlinear hyperbolic
+ * conservation laws":
+ *   - conservation law d_t u + div F(u) = 0, eq. (2ddg), weak form eq.
+ *     (weak2dsys), Euler flux and ideal-gas pressure eq. (euler);
+ *   - each triangle mapped onto the reference triangle {(0,0),(1,0),(0,1)}
+ *     by eq. (2dmap) (counter-clockwise vertices, det J > 0), each edge onto
+ *     [-1,1] by eq. (1dmap) with half length l of eq. (len);
+ *   - orthonormal modal basis of degree p, N_p = (p+1)(p+2)/2 (eq. (np)),
+ *     so the mass matrix is det J times the identity;
+ *   - semi-discrete system eq. (2ddg0): volume integral eq. (volume) with a
+ *     degree-2p symmetric rule, surface integral eq. (surface) with (p+1)
+ *     Gauss-Legendre points per side, numerical flux across each edge.
+ *
+ * Conventions fixed by this library where the paper leaves them open:
+ *   - basis: orthonormal Dubiner polynomials, ordered by total degree and
+ *     then by the degree in s; mode 0 is the constant sqrt(2);
+ *   - local side q of an element runs from its vertex q to vertex q+1;
+ *   - numerical flux: local Lax-Friedrichs at each Gauss point;
+ *   - time integration: three-stage SSP Runge-Kutta (Shu-Osher form);
+ *   - CFL step: dt = cfl * min_i r_i / (|v_i| + c_i), r_i = det J_i /
+ *     perimeter_i (inscribed radius), state at the element mean.
+ *
+ * Memory and streams.  Every pointer named *_dev is device memory owned by
+ * the caller (e.g. a torch tensor); the library never allocates in the calls
+ * that take a stream.  Workspace sizes come from dg_mesh_info.  `stream` is
+ * a hipStream_t passed as void* (NULL = the null stream).  All calls that
+ * take a stream are asynchronous on it unless stated otherwise.  A mesh is
+ * immutable after creation, so calls on different streams with separate
+ * workspaces may overlap.  Results are deterministic: no atomics; every
+ * output is written by exactly one work-item.
+ *
+ * Layouts.
+ *   user layout     C[N][4][N_p], element order of dg_mesh_create, variables
+ *                   (rho, rho u, rho v, E), modes in basis order;
+ *   internal layout the library's own element-blocked order (elements
+ *                   reordered along a space-filling curve, blocks of 64
+ *                   elements, padded to a multiple of 64); state_len doubles.
+ *   dg_pack / dg_unpack convert; dg_rhs, dg_max_dt and dg_rk_step work on
+ *   the internal layout.
+ *
+ * Errors.  Every call returns a dg_status; DG_OK is 0.  dg_last_error()
+ * returns a message for the last failing call of the calling thread.  The
+ * hot calls (dg_rhs, dg_rk_step) do not check the state they are given.
+ */
+#ifndef DGMI_DG_H
+#define DGMI_DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_mesh_s* dg_mesh;
+
+typedef enum {
+    DG_OK = 0,
+    DG_EINVAL = -1,        /* null pointer, bad size or bad enum value */
+    DG_EMESH = -2,         /* invalid mesh (orientation, connectivity, edges) */
+    DG_EORDER = -3,        /* polynomial order outside 1..5 */
+    DG_EUNSUPPORTED = -4,  /* valid input this build does not handle */
+    DG_ENOMEM = -5,        /* device allocation failed */
+    DG_EHIP = -6,          /* a HIP runtime call or kernel launch failed */
+    DG_ENONPHYS = -7       /* non-physical element mean (rho <= 0, p <= 0, NaN) */
+} dg_status;
+
+typedef enum {
+    DG_FP64 = 0,  /* every step in double precision */
+    DG_MIXED = 1  /* reserved: FP32 contractions/flux, FP64 stage update */
+} dg_precision;
+
+typedef struct {
+    int p;              /* polynomial order */
+    int n_modes;        /* N_p = (p+1)(p+2)/2 */
+    int n_vol_points;   /* volume rule size: 3, 6, 12, 16, 25 for p = 1..5 */
+    int n_edge_points;  /* p + 1 */
+    int64_t n_elem;     /* elements */
+    int64_t n_elem_pad; /* elements incl. padding (multiple of 64) */
+    int64_t n_edges;    /* edges (1.5 n_elem on a periodic mesh) */
+    int64_t state_len;  /* doubles in one internal-layout state */
+    int64_t ws_rhs;     /* workspace bytes for dg_rhs and dg_max_dt */
+    int64_t ws_step;    /* workspace bytes for dg_rk_step */
+} dg_info;
+
+/* Checks a mesh without touching the GPU (no HIP call).  Arguments as for
+ * dg_mesh_create.  Returns DG_OK, DG_EINVAL, DG_EORDER, DG_EUNSUPPORTED or
+ * DG_EMESH (the message names the element and side). */
+int dg_mesh_validate(int p, int64_t n_elem, const double* vxy, const int64_t* nbr_elem, const int8_t* nbr_side);
+
+/* Creates a mesh on the current HIP device (Section "Mesh Connectivity"):
+ *   p         polynomial order, 1..5;
+ *   n_elem    number of triangles, >= 1;
+ *   vxy       host [n_elem][3][2] vertex coordinates, counter-clockwise so
+ *             that det J of eq. (2dmap) is positive; periodic meshes give
+ *             every element its own unwrapped coordinates;
+ *   nbr_elem  host [n_elem][3]: element across local side q; a negative
+ *             value is a boundary-condition code (not supported by this
+ *             build: DG_EUNSUPPORTED);
+ *   nbr_side  host [n_elem][3]: that neighbour's local side index;
+ *   gamma     ratio of specific heats (1.4 for air);
+ *   out       receives the handle.
+ * Validates first (see dg_mesh_validate), then builds the edge list (one
+ * entry per edge, left = lower internal id, normal from left to right),
+ * geometry (adj(J), 1/det J, inscribed radius; per-edge unit normal and
+ * half length), the element order and the reference tables, and copies
+ * them to the device.  Synchronous.  The host arrays are not retained. */
+int dg_mesh_create(int p, int64_t n_elem, const double* vxy, const int64_t* nbr_elem, const int8_t* nbr_side,
+                   double gamma, dg_mesh* out);
+
+/* Releases the mesh's device memory.  NULL is accepted. */
+int dg_mesh_destroy(dg_mesh m);
+
+/* Sizes of the mesh's arrays and workspaces. */
+int dg_mesh_info(dg_mesh m, dg_info* out);
+
+/* Physical coordinates of the volume quadrature points, xy_dev [N][n_vol_points][2]
+ * (user element order), for evaluating initial data at them. */
+int dg_quad_points(dg_mesh m, double* xy_dev, void* stream);
+
+/* L2 projection onto the orthonormal basis (mass matrix det J * I):
+ * c_j = sum_k w_k phi_j(r_k) u(x_k).  u_dev [N][n_vol_points][4] holds the
+ * conserved variables at dg_quad_points (user order); C_dev receives the
+ * internal-layout state (padding zeroed). */
+int dg_project(dg_mesh m, const double* u_dev, double* C_dev, void* stream);
+
+/* User layout [N][4][N_p] -> internal layout (padding zeroed), and back. */
+int dg_pack(dg_mesh m, const double* C_user_dev, double* C_dev, void* stream);
+int dg_unpack(dg_mesh m, const double* C_dev, double* C_user_dev, void* stream);
+
+/* Right-hand side of eq. (2ddg0): R = M^{-1} (volume - surface), internal
+ * layout in and out (C_dev and R_dev must not overlap).  ws_dev: ws_rhs
+ * bytes.  prec must be DG_FP64 (DG_MIXED: DG_EUNSUPPORTED in this build). */
+int dg_rhs(dg_mesh m, const double* C_dev, double* R_dev, dg_precision prec, void* ws_dev, void* stream);
+
+/* Stable time step (the paper computes one per step on the device): writes
+ * dt = cfl * min_i r_i / (|v_i| + c_i) to dt_dev[0], or NaN when an element
+ * mean is non-physical.  If dt_host is not NULL the call also copies the
+ * value to *dt_host, waits for the stream, and returns DG_ENONPHYS for NaN.
+ * ws_dev: ws_rhs bytes. */
+int dg_max_dt(dg_mesh m, const double* C_dev, double cfl, double* dt_dev, double* dt_host, void* ws_dev,
+              void* stream);
+
+/* One SSP-RK3 step in place on the internal-layout state C_dev:
+ *   u1 = u + dt L(u);  u2 = 3/4 u + 1/4 (u1 + dt L(u1));
+ *   u  = 1/3 u + 2/3 (u2 + dt L(u2)).
+ * The step length is dt_dev[0] when dt_dev is not NULL (e.g. the output of
+ * dg_max_dt, so a whole step stays on the device), else dt.  ws_dev:
+ * ws_step bytes.  prec as for dg_rhs. */
+int dg_rk_step(dg_mesh m, double* C_dev, double dt, const double* dt_dev, dg_precision prec, void* ws_dev,
+               void* stream);
+
+/* Per-kernel timing (the paper's kernel runtime distribution, measured with
+ * events around every launch).  dg_timing_enable(m, 1) makes every later
+ * launch for this mesh record a pair of HIP events on its stream;
+ * dg_timing_read waits for the recorded events, writes for each kernel kind
+ * k the summed duration in milliseconds ms[k] and the number of launches
+ * count[k] (k = DG_KERNEL_*; arrays of n >= DG_KERNEL_KINDS entries), and
+ * clears the record.  Timing is off by default and adds two event records
+ * per launch when on.  Not thread-safe for one mesh used from several
+ * threads. */
+enum {
+    DG_KERNEL_TRACES = 0,   /* edge traces of a state */
+    DG_KERNEL_EDGE = 1,     /* numerical flux per edge into side slots */
+    DG_KERNEL_ELEMENT = 2,  /* volume + lift + inverse mass (+ RK stage) */
+    DG_KERNEL_DT = 3,       /* CFL reduction (both passes) */
+    DG_KERNEL_KINDS = 4
+};
+int dg_timing_enable(dg_mesh m, int on);
+int dg_timing_read(dg_mesh m, double* ms, int64_t* count, int n);
+
+/* Host-only: the reference tables the kernels use, for checking them on a
+ * machine without a GPU.  Writes into out (capacity cap doubles, in this
+ * order): volume points r[nq], s[nq], weights w[nq]; Gauss nodes x[ne],
+ * weights[ne]; phi[nq][np], dphi/dr[nq][np], dphi/ds[nq][np] at the volume
+ * points; phi at side points [3][ne][np].  Returns the number of doubles
+ * written (> 0), or a negative dg_status. */
+int64_t dg_reference_tables(int p, double* out, int64_t cap);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGMI_DG_H */

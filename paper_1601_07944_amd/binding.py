@@ -1,0 +1,283 @@
+"""ctypes binding of libdgmi (include/dg.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; this module
+passes device pointers of torch tensors and the current HIP stream through
+the C ABI and turns status codes into exceptions.  It never computes any
+part of the method itself and has no CPU fallback: if libdgmi.so is missing
+or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgmi.so")
+
+DG_FP64 = 0
+DG_MIXED = 1
+
+STATUS = {
+    0: "DG_OK",
+    -1: "DG_EINVAL",
+    -2: "DG_EMESH",
+    -3: "DG_EORDER",
+    -4: "DG_EUNSUPPORTED",
+    -5: "DG_ENOMEM",
+    -6: "DG_EHIP",
+    -7: "DG_ENONPHYS",
+}
+
+# Every symbol include/dg.h declares.
+EXPORTS = [
+    "dg_mesh_validate",
+    "dg_mesh_create",
+    "dg_mesh_destroy",
+    "dg_mesh_info",
+    "dg_quad_points",
+    "dg_project",
+    "dg_pack",
+    "dg_unpack",
+    "dg_rhs",
+    "dg_max_dt",
+    "dg_rk_step",
+    "dg_timing_enable",
+    "dg_timing_read",
+    "dg_reference_tables",
+    "dg_last_error",
+]
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class dg_info(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int),
+        ("n_modes", ctypes.c_int),
+        ("n_vol_points", ctypes.c_int),
+        ("n_edge_points", ctypes.c_int),
+        ("n_elem", ctypes.c_int64),
+        ("n_elem_pad", ctypes.c_int64),
+        ("n_edges", ctypes.c_int64),
+        ("state_len", ctypes.c_int64),
+        ("ws_rhs", ctypes.c_int64),
+        ("ws_step", ctypes.c_int64),
+    ]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def load(path: str = LIB_PATH):
+    """Load libdgmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it first (python -m paper_1601_07944_amd.build)")
+    lib = ctypes.CDLL(path)
+    i32, i64 = ctypes.c_int, ctypes.c_int64
+    lib.dg_last_error.restype = ctypes.c_char_p
+    lib.dg_mesh_validate.argtypes = [i32, i64, _vp, _vp, _vp]
+    lib.dg_mesh_create.argtypes = [i32, i64, _vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(_vp)]
+    lib.dg_mesh_destroy.argtypes = [_vp]
+    lib.dg_mesh_info.argtypes = [_vp, ctypes.POINTER(dg_info)]
+    lib.dg_quad_points.argtypes = [_vp, _vp, _vp]
+    lib.dg_project.argtypes = [_vp, _vp, _vp, _vp]
+    lib.dg_pack.argtypes = [_vp, _vp, _vp, _vp]
+    lib.dg_unpack.argtypes = [_vp, _vp, _vp, _vp]
+    lib.dg_rhs.argtypes = [_vp, _vp, _vp, i32, _vp, _vp]
+    lib.dg_max_dt.argtypes = [_vp, _vp, ctypes.c_double, _vp, _dp, _vp, _vp]
+    lib.dg_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _vp, i32, _vp, _vp]
+    lib.dg_timing_enable.argtypes = [_vp, i32]
+    lib.dg_timing_read.argtypes = [_vp, _dp, ctypes.POINTER(i64), i32]
+    lib.dg_reference_tables.argtypes = [i32, _dp, i64]
+    lib.dg_reference_tables.restype = i64
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype or i32
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise DGError(rc, load().dg_last_error().decode())
+    return rc
+
+
+def last_error() -> str:
+    return load().dg_last_error().decode()
+
+
+def validate(p, vxy, nbr_elem, nbr_side):
+    """Host-only mesh check (no HIP call); returns the status code."""
+    vxy = np.ascontiguousarray(vxy, dtype=np.float64)
+    nbr_elem = np.ascontiguousarray(nbr_elem, dtype=np.int64)
+    nbr_side = np.ascontiguousarray(nbr_side, dtype=np.int8)
+    return load().dg_mesh_validate(p, vxy.shape[0], vxy.ctypes.data, nbr_elem.ctypes.data, nbr_side.ctypes.data)
+
+
+def reference_tables(p: int) -> dict:
+    """Host-only: the library's quadrature rules and basis tables."""
+    np_ = (p + 1) * (p + 2) // 2
+    cap = 4096
+    buf = np.zeros(cap)
+    n = load().dg_reference_tables(p, buf.ctypes.data_as(_dp), cap)
+    if n < 0:
+        _check(int(n))
+    nq = {1: 3, 2: 6, 3: 12, 4: 16, 5: 25}[p]
+    ne = p + 1
+    o = 0
+
+    def take(k):
+        nonlocal o
+        a = buf[o : o + k].copy()
+        o += k
+        return a
+
+    out = dict(r=take(nq), s=take(nq), w=take(nq), gx=take(ne), gw=take(ne))
+    out["phi"] = take(nq * np_).reshape(nq, np_)
+    out["dphidr"] = take(nq * np_).reshape(nq, np_)
+    out["dphids"] = take(nq * np_).reshape(nq, np_)
+    out["phi_side"] = take(3 * ne * np_).reshape(3, ne, np_)
+    assert o == n
+    return out
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class DGMesh:
+    """A mesh on the current device (dg_mesh_create); torch tensors carry
+    all device memory.  States passed to rhs / rk_step / max_dt are in the
+    library's internal layout (see pack / unpack)."""
+
+    def __init__(self, p, vxy, nbr_elem, nbr_side, gamma=1.4):
+        import torch
+
+        lib = load()
+        vxy = np.ascontiguousarray(vxy, dtype=np.float64)
+        nbr_elem = np.ascontiguousarray(nbr_elem, dtype=np.int64)
+        nbr_side = np.ascontiguousarray(nbr_side, dtype=np.int8)
+        h = _vp()
+        _check(lib.dg_mesh_create(p, vxy.shape[0], vxy.ctypes.data, nbr_elem.ctypes.data, nbr_side.ctypes.data,
+                                  float(gamma), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        info = dg_info()
+        _check(lib.dg_mesh_info(h, ctypes.byref(info)))
+        self.info = info
+        self.p = p
+        self.n = info.n_elem
+        self.np = info.n_modes
+        self.nq = info.n_vol_points
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._ws = None
+
+    @classmethod
+    def from_mesh(cls, mesh, p, gamma=1.4):
+        return cls(p, mesh.vxy, mesh.nbr_elem, mesh.nbr_side, gamma)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dg_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- allocation helpers (torch owns device memory) --------------------
+    def empty_state(self):
+        import torch
+
+        return torch.empty(self.info.state_len, dtype=torch.float64, device=self.device)
+
+    def workspace(self, kind="step"):
+        import torch
+
+        nbytes = self.info.ws_step if kind == "step" else self.info.ws_rhs
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    # -- entry points -------------------------------------------------------
+    def quad_points(self, stream=None):
+        import torch
+
+        xy = torch.empty((self.n, self.nq, 2), dtype=torch.float64, device=self.device)
+        _check(self._lib.dg_quad_points(self._h, _ptr(xy), _stream(stream)))
+        return xy
+
+    def project(self, u, out=None, stream=None):
+        out = self.empty_state() if out is None else out
+        assert u.is_contiguous() and u.dtype.is_floating_point and u.numel() == self.n * self.nq * 4
+        _check(self._lib.dg_project(self._h, _ptr(u), _ptr(out), _stream(stream)))
+        return out
+
+    def pack(self, C_user, out=None, stream=None):
+        out = self.empty_state() if out is None else out
+        assert C_user.is_contiguous() and C_user.numel() == self.n * 4 * self.np
+        _check(self._lib.dg_pack(self._h, _ptr(C_user), _ptr(out), _stream(stream)))
+        return out
+
+    def unpack(self, C, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty((self.n, 4, self.np), dtype=torch.float64, device=self.device)
+        _check(self._lib.dg_unpack(self._h, _ptr(C), _ptr(out), _stream(stream)))
+        return out
+
+    def rhs(self, C, out=None, prec=DG_FP64, ws=None, stream=None):
+        out = self.empty_state() if out is None else out
+        ws = self.workspace("rhs") if ws is None else ws
+        _check(self._lib.dg_rhs(self._h, _ptr(C), _ptr(out), prec, _ptr(ws), _stream(stream)))
+        return out
+
+    def max_dt(self, C, cfl, dt_dev=None, to_host=True, ws=None, stream=None):
+        """Returns (dt_dev tensor, host float or None)."""
+        import torch
+
+        dt_dev = torch.empty(1, dtype=torch.float64, device=self.device) if dt_dev is None else dt_dev
+        ws = self.workspace("rhs") if ws is None else ws
+        host = ctypes.c_double(0.0)
+        _check(self._lib.dg_max_dt(self._h, _ptr(C), float(cfl), _ptr(dt_dev),
+                                   ctypes.byref(host) if to_host else None, _ptr(ws), _stream(stream)))
+        return dt_dev, (host.value if to_host else None)
+
+    KERNELS = ("traces", "edge", "element", "dt")
+
+    def timing(self, on: bool):
+        _check(self._lib.dg_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self):
+        """{kernel kind: (total ms, launches)} since the last read (waits)."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        _check(self._lib.dg_timing_read(self._h, ms, cnt, 4))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
+
+    def rk_step(self, C, dt=0.0, dt_dev=None, prec=DG_FP64, ws=None, stream=None):
+        ws = self.workspace("step") if ws is None else ws
+        _check(self._lib.dg_rk_step(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None, prec,
+                                    _ptr(ws), _stream(stream)))
+        return C

@@ -1,0 +1,493 @@
+// C ABI of libdgmi (declared in include/dg.h): mesh preprocessing on the
+// host and orchestration of the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "dg_internal.h"
+
+struct dg_mesh_s {
+    dgk::MeshDev dev;
+    dgh::TableLayout lay;
+    int64_t ws_rhs = 0, ws_step = 0;
+    // workspace offsets (bytes)
+    size_t off_T0 = 0, off_T1 = 0, off_S = 0, off_part = 0, off_u1 = 0, off_u2 = 0;
+    std::vector<void*> allocs;
+    // per-launch event timing (dg_timing_*)
+    bool timing = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok()
+{
+    g_err.clear();
+    return DG_OK;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(DG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int n_vol_points(int p)
+{
+    static const int nq[6] = {0, 3, 6, 12, 16, 25};
+    return nq[p];
+}
+
+// 21-bit interleave for a 42-bit Morton key
+uint64_t spread(uint64_t v)
+{
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+
+int dg_mesh_validate(int p, int64_t n, const double* vxy, const int64_t* nbr, const int8_t* nbs)
+{
+    if (p < 1 || p > 5) return fail(DG_EORDER, "order p=%d outside 1..5", p);
+    if (n < 1 || !vxy || !nbr || !nbs) return fail(DG_EINVAL, "n_elem must be >= 1 and all arrays non-null");
+    const int64_t npad = (n + 63) / 64 * 64;
+    const int np = dgh::n_modes(p);
+    if (npad * std::max(4 * np, 12 * (p + 1)) >= (int64_t(1) << 31))
+        return fail(DG_EUNSUPPORTED, "mesh too large for 32-bit element indexing (%lld elements at p=%d)",
+                    (long long)n, p);
+    for (int64_t i = 0; i < n; ++i) {
+        const double* v = vxy + 6 * i;
+        for (int c = 0; c < 6; ++c)
+            if (!std::isfinite(v[c])) return fail(DG_EMESH, "element %lld: non-finite vertex coordinate", (long long)i);
+        double det = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
+        if (!(det > 0.0))
+            return fail(DG_EMESH, "element %lld: det J = %g <= 0 (vertices must be counter-clockwise)", (long long)i,
+                        det);
+        for (int q = 0; q < 3; ++q) {
+            int64_t j = nbr[3 * i + q];
+            if (j < 0)
+                return fail(DG_EUNSUPPORTED, "element %lld side %d: boundary code %lld (only interior/periodic "
+                                             "connectivity is supported)",
+                            (long long)i, q, (long long)j);
+            if (j >= n) return fail(DG_EMESH, "element %lld side %d: neighbour %lld out of range", (long long)i, q,
+                                    (long long)j);
+            int qn = nbs[3 * i + q];
+            if (qn < 0 || qn > 2)
+                return fail(DG_EMESH, "element %lld side %d: neighbour side %d outside 0..2", (long long)i, q, qn);
+            if (nbr[3 * j + qn] != i || nbs[3 * j + qn] != q)
+                return fail(DG_EMESH, "element %lld side %d: neighbour %lld side %d does not point back", (long long)i,
+                            q, (long long)j, qn);
+            if (j == i && qn == q) return fail(DG_EMESH, "element %lld side %d is its own neighbour", (long long)i, q);
+            // the two copies of the edge must be the same segment traversed in
+            // opposite directions (up to a periodic shift)
+            const double* w = vxy + 6 * j;
+            double ex = v[2 * ((q + 1) % 3)] - v[2 * q], ey = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
+            double fx = w[2 * ((qn + 1) % 3)] - w[2 * qn], fy = w[2 * ((qn + 1) % 3) + 1] - w[2 * qn + 1];
+            double len = std::sqrt(ex * ex + ey * ey);
+            if (std::fabs(ex + fx) > 1e-12 * len || std::fabs(ey + fy) > 1e-12 * len)
+                return fail(DG_EMESH, "element %lld side %d and element %lld side %d are not the same edge",
+                            (long long)i, q, (long long)j, qn);
+        }
+    }
+    return ok();
+}
+
+int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, const int8_t* nbs, double gamma,
+                   dg_mesh* out)
+{
+    if (!out) return fail(DG_EINVAL, "out is null");
+    *out = nullptr;
+    int rc = dg_mesh_validate(p, n, vxy, nbr, nbs);
+    if (rc != DG_OK) return rc;
+    if (!(gamma > 1.0)) return fail(DG_EINVAL, "gamma must be > 1");
+
+    const int np = dgh::n_modes(p), ne = p + 1, nq = n_vol_points(p);
+    const int N = (int)n, npad = (N + 63) / 64 * 64;
+
+    // element order along a Morton curve of the centroids
+    std::vector<double> cx(N), cy(N);
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (int i = 0; i < N; ++i) {
+        const double* v = vxy + 6 * i;
+        cx[i] = (v[0] + v[2] + v[4]) / 3.0;
+        cy[i] = (v[1] + v[3] + v[5]) / 3.0;
+        xmin = std::min(xmin, cx[i]);
+        xmax = std::max(xmax, cx[i]);
+        ymin = std::min(ymin, cy[i]);
+        ymax = std::max(ymax, cy[i]);
+    }
+    const double span = std::max(std::max(xmax - xmin, ymax - ymin), 1e-300);
+    std::vector<uint64_t> key(N);
+    for (int i = 0; i < N; ++i) {
+        uint64_t qx = (uint64_t)std::min(2097151.0, std::floor((cx[i] - xmin) / span * 2097151.0));
+        uint64_t qy = (uint64_t)std::min(2097151.0, std::floor((cy[i] - ymin) / span * 2097151.0));
+        key[i] = spread(qx) | (spread(qy) << 1);
+    }
+    std::vector<int> perm(N), inv(N);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    for (int i = 0; i < N; ++i) inv[perm[i]] = i;
+
+    // geometry [blk][6][64] and vertices (internal order)
+    std::vector<double> geo((size_t)npad * 6, 0.0), vtx((size_t)npad * 6, 0.0);
+    for (int i = 0; i < N; ++i) {
+        const double* v = vxy + 6 * perm[i];
+        const double x1 = v[0], y1 = v[1], x2 = v[2], y2 = v[3], x3 = v[4], y3 = v[5];
+        const double det = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
+        double per = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            double dx = v[2 * ((q + 1) % 3)] - v[2 * q], dy = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
+            per += std::sqrt(dx * dx + dy * dy);
+        }
+        const size_t b = (size_t)(i / 64) * 6 * 64 + (i % 64);
+        geo[b + 0 * 64] = y3 - y1;     // adj(J) = det J * J^{-1}
+        geo[b + 1 * 64] = -(x3 - x1);
+        geo[b + 2 * 64] = -(y2 - y1);
+        geo[b + 3 * 64] = x2 - x1;
+        geo[b + 4 * 64] = 1.0 / det;
+        geo[b + 5 * 64] = det / per;   // inscribed radius
+        std::memcpy(&vtx[(size_t)i * 6], v, 6 * sizeof(double));
+    }
+
+    // edges: one per element pair, left = lower internal id, sorted by left
+    std::vector<int> el, er, sd;
+    std::vector<double> egx, egy, egl;
+    el.reserve(3 * N / 2 + 1);
+    for (int i = 0; i < N; ++i) {
+        const int u = perm[i];
+        const double* v = vxy + 6 * u;
+        for (int q = 0; q < 3; ++q) {
+            const int j = inv[nbr[3 * u + q]];
+            const int qn = nbs[3 * u + q];
+            if (j < i || (j == i && qn < q)) continue;
+            double dx = v[2 * ((q + 1) % 3)] - v[2 * q], dy = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
+            double len = std::sqrt(dx * dx + dy * dy);
+            el.push_back(i);
+            er.push_back(j);
+            sd.push_back(q | (qn << 2));
+            egx.push_back(dy / len);
+            egy.push_back(-dx / len);
+            egl.push_back(0.5 * len);
+        }
+    }
+    const int nedge = (int)el.size();
+    std::vector<double> eg(3 * (size_t)nedge);
+    for (int i = 0; i < nedge; ++i) {
+        eg[i] = egx[i];
+        eg[nedge + i] = egy[i];
+        eg[2 * (size_t)nedge + i] = egl[i];
+    }
+
+    dgh::TableLayout lay;
+    std::vector<double> tab = dgh::build_tables(p, &lay);
+    if (!dgk::table_offset_check(p, lay) || lay.nq != nq)
+        return fail(DG_EUNSUPPORTED, "internal error: table layout mismatch at p=%d", p);
+
+    dg_mesh m = new dg_mesh_s();
+    auto upload = [&](const void* src, size_t bytes, void** dst) -> int {
+        void* d = nullptr;
+        hipError_t e = hipMalloc(&d, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EHIP, "hipMalloc(%zu): %s", bytes,
+                                         hipGetErrorString(e));
+        m->allocs.push_back(d);
+        if (bytes) {
+            e = hipMemcpy(d, src, bytes, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        }
+        *dst = d;
+        return DG_OK;
+    };
+    void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg;
+    if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
+        (rc = upload(vtx.data(), vtx.size() * 8, &d_vtx)) || (rc = upload(perm.data(), perm.size() * 4, &d_perm)) ||
+        (rc = upload(el.data(), el.size() * 4, &d_el)) || (rc = upload(er.data(), er.size() * 4, &d_er)) ||
+        (rc = upload(sd.data(), sd.size() * 4, &d_sd)) || (rc = upload(eg.data(), eg.size() * 8, &d_eg))) {
+        std::string msg = g_err;
+        dg_mesh_destroy(m);
+        return fail(rc, "%s", msg.c_str());
+    }
+    dgk::MeshDev& d = m->dev;
+    d.p = p;
+    d.np = np;
+    d.nq = nq;
+    d.ne = ne;
+    d.n = N;
+    d.npad = npad;
+    d.nedge = nedge;
+    d.gamma = gamma;
+    d.tab = (const double*)d_tab;
+    d.geo = (const double*)d_geo;
+    d.vtx = (const double*)d_vtx;
+    d.perm = (const int*)d_perm;
+    d.edge_l = (const int*)d_el;
+    d.edge_r = (const int*)d_er;
+    d.edge_sd = (const int*)d_sd;
+    d.edge_g = (const double*)d_eg;
+    m->lay = lay;
+
+    const size_t state = align256((size_t)npad * 4 * np * 8);
+    const size_t trace = align256((size_t)npad * 3 * ne * 4 * 8);
+    const size_t part = align256((size_t)dgk::dt_partials(d) * 8);
+    m->off_T0 = 0;
+    m->off_S = trace;
+    m->off_part = 2 * trace;
+    m->ws_rhs = (int64_t)(2 * trace + part);
+    m->off_T1 = 2 * trace + part;
+    m->off_u1 = 3 * trace + part;
+    m->off_u2 = 3 * trace + part + state;
+    m->ws_step = (int64_t)(3 * trace + part + 2 * state);
+    *out = m;
+    return ok();
+}
+
+int dg_mesh_destroy(dg_mesh m)
+{
+    if (!m) return ok();
+    for (auto& r : m->recs) {
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : m->pool) (void)hipEventDestroy(e);
+    for (void* p : m->allocs) (void)hipFree(p);
+    delete m;
+    return ok();
+}
+
+int dg_mesh_info(dg_mesh m, dg_info* out)
+{
+    if (!m || !out) return fail(DG_EINVAL, "null argument");
+    out->p = m->dev.p;
+    out->n_modes = m->dev.np;
+    out->n_vol_points = m->dev.nq;
+    out->n_edge_points = m->dev.ne;
+    out->n_elem = m->dev.n;
+    out->n_elem_pad = m->dev.npad;
+    out->n_edges = m->dev.nedge;
+    out->state_len = (int64_t)m->dev.npad * 4 * m->dev.np;
+    out->ws_rhs = m->ws_rhs;
+    out->ws_step = m->ws_step;
+    return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+hipEvent_t take_event(dg_mesh m)
+{
+    if (!m->pool.empty()) {
+        hipEvent_t e = m->pool.back();
+        m->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Runs `launch` on stream s, bracketed by events when timing is on.
+template <class F>
+void timed(dg_mesh m, int kind, hipStream_t s, F&& launch)
+{
+    if (!m->timing) {
+        launch();
+        return;
+    }
+    dg_mesh_s::Rec r{kind, take_event(m), take_event(m)};
+    (void)hipEventRecord(r.a, s);
+    launch();
+    (void)hipEventRecord(r.b, s);
+    m->recs.push_back(r);
+}
+
+}  // namespace
+
+extern "C" {
+
+static int check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return ok();
+}
+
+int dg_quad_points(dg_mesh m, double* xy, void* stream)
+{
+    if (!m || !xy) return fail(DG_EINVAL, "null argument");
+    dgk::launch_quad_points(m->dev, xy, (hipStream_t)stream);
+    return check_launch("dg_quad_points");
+}
+
+int dg_project(dg_mesh m, const double* u, double* C, void* stream)
+{
+    if (!m || !u || !C) return fail(DG_EINVAL, "null argument");
+    dgk::launch_project(m->dev, u, C, (hipStream_t)stream);
+    return check_launch("dg_project");
+}
+
+int dg_pack(dg_mesh m, const double* Cu, double* C, void* stream)
+{
+    if (!m || !Cu || !C) return fail(DG_EINVAL, "null argument");
+    dgk::launch_pack(m->dev, Cu, C, (hipStream_t)stream);
+    return check_launch("dg_pack");
+}
+
+int dg_unpack(dg_mesh m, const double* C, double* Cu, void* stream)
+{
+    if (!m || !C || !Cu) return fail(DG_EINVAL, "null argument");
+    dgk::launch_unpack(m->dev, C, Cu, (hipStream_t)stream);
+    return check_launch("dg_unpack");
+}
+
+int dg_rhs(dg_mesh m, const double* C, double* R, dg_precision prec, void* ws, void* stream)
+{
+    if (!m || !C || !R || !ws) return fail(DG_EINVAL, "null argument");
+    if (prec != DG_FP64) return fail(prec == DG_MIXED ? DG_EUNSUPPORTED : DG_EINVAL, "precision %d not available", prec);
+    char* w = (char*)ws;
+    double* T = (double*)(w + m->off_T0);
+    double* S = (double*)(w + m->off_S);
+    hipStream_t s = (hipStream_t)stream;
+    timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s); });
+    timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(m->dev, T, S, s); });
+    timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(m->dev, 0, C, nullptr, R, S, 0.0, nullptr, nullptr, s); });
+    return check_launch("dg_rhs");
+}
+
+int dg_max_dt(dg_mesh m, const double* C, double cfl, double* dt_dev, double* dt_host, void* ws, void* stream)
+{
+    if (!m || !C || !dt_dev || !ws) return fail(DG_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    timed(m, DG_KERNEL_DT, s, [&] { dgk::launch_dt(m->dev, C, cfl, (double*)((char*)ws + m->off_part), dt_dev, s); });
+    int rc = check_launch("dg_max_dt");
+    if (rc != DG_OK || !dt_host) return rc;
+    hipError_t e = hipMemcpyAsync(dt_host, dt_dev, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "dg_max_dt copy");
+    if (std::isnan(*dt_host)) return fail(DG_ENONPHYS, "non-physical element mean (rho <= 0, p <= 0 or NaN)");
+    return ok();
+}
+
+int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precision prec, void* ws, void* stream)
+{
+    if (!m || !C || !ws) return fail(DG_EINVAL, "null argument");
+    if (prec != DG_FP64) return fail(prec == DG_MIXED ? DG_EUNSUPPORTED : DG_EINVAL, "precision %d not available", prec);
+    char* w = (char*)ws;
+    double* T0 = (double*)(w + m->off_T0);
+    double* T1 = (double*)(w + m->off_T1);
+    double* S = (double*)(w + m->off_S);
+    double* u1 = (double*)(w + m->off_u1);
+    double* u2 = (double*)(w + m->off_u2);
+    hipStream_t s = (hipStream_t)stream;
+    const dgk::MeshDev& d = m->dev;
+    timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s); });
+    timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, T0, S, s); });
+    timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 1, C, nullptr, u1, S, dt, dt_dev, T1, s); });
+    timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, T1, S, s); });
+    timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 2, u1, C, u2, S, dt, dt_dev, T0, s); });
+    timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, T0, S, s); });
+    timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 3, u2, C, C, S, dt, dt_dev, nullptr, s); });
+    return check_launch("dg_rk_step");
+}
+
+int dg_timing_enable(dg_mesh m, int on)
+{
+    if (!m) return fail(DG_EINVAL, "null mesh");
+    m->timing = on != 0;
+    return ok();
+}
+
+int dg_timing_read(dg_mesh m, double* ms, int64_t* count, int n)
+{
+    if (!m || !ms || !count || n < DG_KERNEL_KINDS) return fail(DG_EINVAL, "bad arguments");
+    for (int k = 0; k < n; ++k) {
+        ms[k] = 0.0;
+        count[k] = 0;
+    }
+    int rc = DG_OK;
+    for (auto& r : m->recs) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess && rc == DG_OK) rc = hip_fail(e, "dg_timing_read");
+        ms[r.kind] += t;
+        count[r.kind] += 1;
+        m->pool.push_back(r.a);
+        m->pool.push_back(r.b);
+    }
+    m->recs.clear();
+    return rc == DG_OK ? ok() : rc;
+}
+
+int64_t dg_reference_tables(int p, double* out, int64_t cap)
+{
+    if (p < 1 || p > 5) return fail(DG_EORDER, "order p=%d outside 1..5", p);
+    if (!out) return fail(DG_EINVAL, "null argument");
+    std::vector<double> r, s, w, gx, gw;
+    dgh::volume_rule(p, r, s, w);
+    dgh::gauss_rule(p + 1, gx, gw);
+    const int np = dgh::n_modes(p), nq = (int)r.size(), ne = p + 1;
+    const int64_t need = 3 * nq + 2 * ne + 3 * nq * np + 3 * ne * np;
+    if (cap < need) return fail(DG_EINVAL, "capacity %lld < %lld", (long long)cap, (long long)need);
+    double* o = out;
+    for (int k = 0; k < nq; ++k) *o++ = r[k];
+    for (int k = 0; k < nq; ++k) *o++ = s[k];
+    for (int k = 0; k < nq; ++k) *o++ = w[k];
+    for (int k = 0; k < ne; ++k) *o++ = gx[k];
+    for (int k = 0; k < ne; ++k) *o++ = gw[k];
+    std::vector<double> phi(np), dr(np), ds(np);
+    double* P = o;
+    double* DR = o + nq * np;
+    double* DS = o + 2 * nq * np;
+    for (int k = 0; k < nq; ++k) {
+        dgh::basis_eval(p, r[k], s[k], P + k * np, DR + k * np, DS + k * np);
+    }
+    o += 3 * nq * np;
+    for (int q = 0; q < 3; ++q)
+        for (int k = 0; k < ne; ++k) {
+            double rr, ss;
+            dgh::side_point(q, gx[k], &rr, &ss);
+            dgh::basis_eval(p, rr, ss, o + (q * ne + k) * np, nullptr, nullptr);
+        }
+    ok();
+    return need;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Internal declarations shared by the host code and the HIP kernels of
+// libdgmi.  Not part of the public ABI (that is include/dg.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace dgh {
+
+// Offsets (in doubles) of the reference tables inside one device buffer.
+struct TableLayout {
+    int np = 0, nq = 0, ne = 0;
+    int phi = 0, drw = 0, dsw = 0, phs = 0, gw = 0, qw = 0, qr = 0, qs = 0, size = 0;
+};
+
+int n_modes(int p);
+void basis_eval(int p, double r, double s, double* phi, double* dr, double* ds);
+void volume_rule(int p, std::vector<double>& r, std::vector<double>& s, std::vector<double>& w);
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
+void side_point(int q, double xi, double* r, double* s);
+std::vector<double> build_tables(int p, TableLayout* lay);
+
+}  // namespace dgh
+
+namespace dgk {
+
+// Elements are processed in blocks of 64 (one wavefront); every per-element
+// array is stored block-major: [block][field][lane], lane = element % 64.
+constexpr int LANES = 64;
+
+// Device view of a mesh, passed by value to the launchers.
+struct MeshDev {
+    int p = 0, np = 0, nq = 0, ne = 0;
+    int n = 0;         // real elements
+    int npad = 0;      // padded to a multiple of 64
+    int nedge = 0;
+    double gamma = 1.4;
+    const double* tab = nullptr;      // reference tables (TableLayout)
+    const double* geo = nullptr;      // [blk][6][64]: adj00 adj01 adj10 adj11 1/detJ r_in
+    const double* vtx = nullptr;      // [npad][6] vertices (internal order), setup only
+    const int* perm = nullptr;        // internal -> user element id
+    const int* edge_l = nullptr;      // [nedge] left element (internal id)
+    const int* edge_r = nullptr;      // [nedge] right element
+    const int* edge_sd = nullptr;     // [nedge] side_l | side_r << 2
+    const double* edge_g = nullptr;   // SoA [3][nedge]: unit normal (left -> right) x, y; half length
+};
+
+// Launchers (dg_kernels.hip).  All asynchronous on `s`.
+void launch_traces(const MeshDev& m, const double* C, double* T, hipStream_t s);
+void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s);
+// mode 0: R = L(C);   mode 1..3: SSP-RK3 stage (out = stage result);
+// when Tnext != nullptr the traces of `out` are written to it.
+void launch_element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
+                    double dt, const double* dt_dev, double* Tnext, hipStream_t s);
+void launch_dt(const MeshDev& m, const double* C, double cfl, double* partial, double* dt_dev, hipStream_t s);
+int dt_partials(const MeshDev& m);
+void launch_pack(const MeshDev& m, const double* Cu, double* C, hipStream_t s);
+void launch_unpack(const MeshDev& m, const double* C, double* Cu, hipStream_t s);
+void launch_project(const MeshDev& m, const double* uq, double* C, hipStream_t s);
+void launch_quad_points(const MeshDev& m, double* xy, hipStream_t s);
+int table_offset_check(int p, const dgh::TableLayout& L);
+
+}  // namespace dgk

@@ -1,0 +1,387 @@
+// HIP kernels (gfx950) of the modal DG right-hand side for the 2D Euler
+// equations, eq. (2ddg0) with the flux of eq. (euler).
+//
+// Data layout.  Modal coefficients are element-blocked structure of arrays:
+// C[blk][m][j][lane] with 64 elements (one wavefront) per block, so that a
+// wavefront reading mode j of variable m touches 512 contiguous bytes.  Edge
+// traces and per-side surface fluxes use the same blocking:
+// T[blk][q][k][m][lane] (side q of the element, edge point k).
+//
+// Kernels (one work-item per element or per edge, wave64):
+//   k_traces   U at the p+1 Gauss points of the three sides of each element
+//              (the side loop is uniform across the wavefront, so the basis
+//              tables are read through scalar loads);
+//   k_edge     per edge: gathers the two traces (the right element's at the
+//              reversed point, Section "Surface Integration Kernel"),
+//              evaluates the local Lax-Friedrichs flux once and stores it,
+//              scaled by l*omega_k, into one slot per element side (one
+//              writer per slot, no atomics: the paper's left/right
+//              temporaries, kept per side);
+//   k_element  per element: volume integral eq. (volume) at the degree-2p
+//              points, lift of its three side slots, multiplication by the
+//              inverse mass matrix 1/det J (orthonormal basis), and either a
+//              plain RHS store or a fused SSP-RK3 stage update; for RK
+//              stages it also writes the traces of the updated state so the
+//              next stage needs no trace pass;
+//   k_dt_*     deterministic two-pass min reduction of the CFL step.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dg_internal.h"
+
+namespace dgk {
+
+template <int P>
+struct Ord {
+    static constexpr int NP = (P + 1) * (P + 2) / 2;
+    static constexpr int NQ = P == 1 ? 3 : P == 2 ? 6 : P == 3 ? 12 : P == 4 ? 16 : 25;
+    static constexpr int NE = P + 1;
+    // table offsets, identical to the host layout (checked at mesh creation)
+    static constexpr int PHI = 0;
+    static constexpr int DRW = PHI + NQ * NP;
+    static constexpr int DSW = DRW + NQ * NP;
+    static constexpr int PHS = DSW + NQ * NP;
+    static constexpr int GW = PHS + 3 * NE * NP;
+    static constexpr int QW = GW + NE;
+    static constexpr int QR = QW + NQ;
+    static constexpr int QS = QR + NQ;
+};
+
+constexpr int BLOCK = 256;
+
+__device__ __forceinline__ int state_off(int e, int nfield) { return (e >> 6) * nfield * LANES + (e & 63); }
+
+// ---------------------------------------------------------------- physics
+// Euler flux eq. (euler) at one point; p = (gamma-1)(E - rho |v|^2 / 2).
+__device__ __forceinline__ void euler_flux(double gm1, const double U[4], double Fx[4], double Fy[4])
+{
+    const double ri = 1.0 / U[0];
+    const double u = U[1] * ri, v = U[2] * ri;
+    const double p = gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
+    Fx[0] = U[1];
+    Fx[1] = U[1] * u + p;
+    Fx[2] = U[2] * u;
+    Fx[3] = u * (U[3] + p);
+    Fy[0] = U[2];
+    Fy[1] = U[1] * v;
+    Fy[2] = U[2] * v + p;
+    Fy[3] = v * (U[3] + p);
+}
+
+// Local Lax-Friedrichs flux across unit normal n (from L to R):
+// Fn = (F(UL).n + F(UR).n)/2 - lambda/2 (UR - UL),
+// lambda = max(|vL.n| + cL, |vR.n| + cR).  Exchanging L and R and negating n
+// negates Fn bitwise.
+__device__ __forceinline__ void llf(double gamma, double gm1, const double UL[4], const double UR[4], double nx,
+                                    double ny, double Fn[4])
+{
+    const double riL = 1.0 / UL[0], riR = 1.0 / UR[0];
+    const double uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
+    const double pL = gm1 * (UL[3] - 0.5 * (UL[1] * uL + UL[2] * vL));
+    const double pR = gm1 * (UR[3] - 0.5 * (UR[1] * uR + UR[2] * vR));
+    const double vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
+    const double lamL = fabs(vnL) + sqrt(gamma * pL * riL);
+    const double lamR = fabs(vnR) + sqrt(gamma * pR * riR);
+    const double lam = fmax(lamL, lamR);
+    const double fL[4] = {UL[0] * vnL, UL[1] * vnL + pL * nx, UL[2] * vnL + pL * ny, (UL[3] + pL) * vnL};
+    const double fR[4] = {UR[0] * vnR, UR[1] * vnR + pR * nx, UR[2] * vnR + pR * ny, (UR[3] + pR) * vnR};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Fn[m] = 0.5 * (fL[m] + fR[m]) - 0.5 * lam * (UR[m] - UL[m]);
+}
+
+// ---------------------------------------------------------------- traces
+template <int P>
+__device__ __forceinline__ void store_traces(const double (&c)[4][Ord<P>::NP], const double* __restrict__ tab,
+                                             double* __restrict__ t0)
+{
+    using O = Ord<P>;
+#pragma unroll
+    for (int qk = 0; qk < 3 * O::NE; ++qk) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double u = 0.0;
+#pragma unroll
+            for (int j = 0; j < O::NP; ++j) u = fma(tab[O::PHS + qk * O::NP + j], c[m][j], u);
+            t0[(qk * 4 + m) * LANES] = u;
+        }
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_traces(int n, const double* __restrict__ C, double* __restrict__ T,
+                                                  const double* __restrict__ tab)
+{
+    using O = Ord<P>;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= n) return;
+    const double* c0 = C + state_off(e, 4 * O::NP);
+    double c[4][O::NP];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < O::NP; ++j) c[m][j] = c0[(m * O::NP + j) * LANES];
+    store_traces<P>(c, tab, T + state_off(e, 3 * O::NE * 4));
+}
+
+// ---------------------------------------------------------------- edges
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_edge(int nedge, const int* __restrict__ el, const int* __restrict__ er,
+                                                const int* __restrict__ sd, const double* __restrict__ eg,
+                                                const double* __restrict__ T, double* __restrict__ S,
+                                                const double* __restrict__ tab, double gamma)
+{
+    using O = Ord<P>;
+    constexpr int NE = O::NE;
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= nedge) return;
+    const int l = el[i], r = er[i], sides = sd[i];
+    const int ql = sides & 3, qr = (sides >> 2) & 3;
+    const double nx = eg[i], ny = eg[nedge + i], hl = eg[2 * nedge + i];
+    const int offl = state_off(l, 3 * NE * 4) + ql * NE * 4 * LANES;
+    const int offr = state_off(r, 3 * NE * 4) + qr * NE * 4 * LANES;
+    const double gm1 = gamma - 1.0;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int kr = NE - 1 - k;
+        double UL[4], UR[4], F[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            UL[m] = T[offl + (k * 4 + m) * LANES];
+            UR[m] = T[offr + (kr * 4 + m) * LANES];
+        }
+        llf(gamma, gm1, UL, UR, nx, ny, F);
+        const double w = hl * tab[O::GW + k];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            S[offl + (k * 4 + m) * LANES] = -w * F[m];
+            S[offr + (kr * 4 + m) * LANES] = w * F[m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- elements
+template <int P, int MODE, bool TRACE>
+__global__ __launch_bounds__(BLOCK) void k_element(int n, const double* __restrict__ C, const double* U0, double* out,
+                                                   const double* __restrict__ S, const double* __restrict__ geo,
+                                                   const double* __restrict__ tab, double gm1, double dt,
+                                                   const double* __restrict__ dt_dev, double* __restrict__ Tn)
+{
+    using O = Ord<P>;
+    constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= n) return;
+    const int so = state_off(e, 4 * NP);
+    const double* g = geo + state_off(e, 6);
+    const double a00 = g[0], a01 = g[LANES], a10 = g[2 * LANES], a11 = g[3 * LANES], idet = g[4 * LANES];
+
+    double c[4][NP];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) c[m][j] = C[so + (m * NP + j) * LANES];
+
+    double acc[4][NP];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) acc[m][j] = 0.0;
+
+    // volume integral: sum_k w_k grad phi_j(r_k) . (adj(J) F(U(r_k)));
+    // the point loop stays rolled so only one point's table rows are live
+#pragma unroll 1
+    for (int k = 0; k < NQ; ++k) {
+        double U[4], Fx[4], Fy[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double u = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) u = fma(tab[O::PHI + k * NP + j], c[m][j], u);
+            U[m] = u;
+        }
+        euler_flux(gm1, U, Fx, Fy);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double gr = a00 * Fx[m] + a01 * Fy[m];
+            const double gs = a10 * Fx[m] + a11 * Fy[m];
+#pragma unroll
+            for (int j = 0; j < NP; ++j)
+                acc[m][j] = fma(tab[O::DRW + k * NP + j], gr, fma(tab[O::DSW + k * NP + j], gs, acc[m][j]));
+        }
+    }
+
+    // surface integral: lift the three side slots (already l * omega_k * Fn)
+    const int to = state_off(e, 3 * NE * 4);
+#pragma unroll 1
+    for (int qk = 0; qk < 3 * NE; ++qk) {
+        double sv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) sv[m] = S[to + (qk * 4 + m) * LANES];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) acc[m][j] = fma(tab[O::PHS + qk * NP + j], sv[m], acc[m][j]);
+    }
+
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) out[so + (m * NP + j) * LANES] = idet * acc[m][j];
+    } else {
+        const double h = dt_dev ? dt_dev[0] : dt;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const double L = idet * acc[m][j];
+                double v;
+                if constexpr (MODE == 1) {
+                    v = c[m][j] + h * L;
+                } else if constexpr (MODE == 2) {
+                    v = 0.75 * U0[so + (m * NP + j) * LANES] + 0.25 * (c[m][j] + h * L);
+                } else {
+                    v = (1.0 / 3.0) * U0[so + (m * NP + j) * LANES] + (2.0 / 3.0) * (c[m][j] + h * L);
+                }
+                out[so + (m * NP + j) * LANES] = v;
+                c[m][j] = v;
+            }
+        if constexpr (TRACE) store_traces<P>(c, tab, Tn + to);
+    }
+}
+
+// ---------------------------------------------------------------- CFL step
+// dt = cfl * min_i r_i / (|v_i| + c_i) over cell averages sqrt(2) c_{i,0};
+// a non-physical or NaN mean makes the result NaN.  min is exact, so the
+// two-pass reduction is bitwise reproducible.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_dt_partial(int n, const double* __restrict__ C, const double* __restrict__ geo,
+                                                      double gamma, double* __restrict__ partial)
+{
+    using O = Ord<P>;
+    __shared__ double red[BLOCK];
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    double val = INFINITY;
+    if (e < n) {
+        const int so = state_off(e, 4 * O::NP);
+        const double s2 = 1.4142135623730951;
+        const double rho = s2 * C[so], mx = s2 * C[so + O::NP * LANES], my = s2 * C[so + 2 * O::NP * LANES],
+                     E = s2 * C[so + 3 * O::NP * LANES];
+        const double u = mx / rho, v = my / rho;
+        const double p = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+        const double rin = geo[state_off(e, 6) + 5 * LANES];
+        if (rho > 0.0 && p > 0.0) {
+            val = rin / (sqrt(u * u + v * v) + sqrt(gamma * p / rho));
+        } else {
+            val = -1.0;  // non-physical (also catches NaN)
+        }
+    }
+    red[threadIdx.x] = val;
+    __syncthreads();
+#pragma unroll
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// L2 projection of point values (user order [N][NQ][4]) onto the
+// orthonormal basis: c_j = sum_k w_k phi_j(r_k) u_k (mass = det J * I).
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_project(int n, int npad, const int* __restrict__ perm,
+                                                   const double* __restrict__ uq, double* __restrict__ C,
+                                                   const double* __restrict__ tab)
+{
+    using O = Ord<P>;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= npad) return;
+    const int so = state_off(e, 4 * O::NP);
+    if (e >= n) {
+        for (int x = 0; x < 4 * O::NP; ++x) C[so + x * LANES] = 0.0;
+        return;
+    }
+    const double* u = uq + (size_t)perm[e] * O::NQ * 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < O::NP; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < O::NQ; ++k) s = fma(tab[O::QW + k] * tab[O::PHI + k * O::NP + j], u[k * 4 + m], s);
+            C[so + (m * O::NP + j) * LANES] = s;
+        }
+}
+
+// physical volume points, user order [N][NQ][2]
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_quad_points(int n, const int* __restrict__ perm,
+                                                       const double* __restrict__ vtx, double* __restrict__ xy,
+                                                       const double* __restrict__ tab)
+{
+    using O = Ord<P>;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= n) return;
+    const double* v = vtx + (size_t)e * 6;
+    double* o = xy + (size_t)perm[e] * O::NQ * 2;
+    for (int k = 0; k < O::NQ; ++k) {
+        const double r = tab[O::QR + k], s = tab[O::QS + k], l1 = 1.0 - r - s;
+        o[2 * k] = v[0] * l1 + v[2] * r + v[4] * s;
+        o[2 * k + 1] = v[1] * l1 + v[3] * r + v[5] * s;
+    }
+}
+
+// ---------------------------------------------------------------- per-order launchers
+static inline dim3 grid_for(int n) { return dim3((n + BLOCK - 1) / BLOCK); }
+
+template <int P>
+struct Launch {
+    static void traces(const MeshDev& m, const double* C, double* T, hipStream_t s)
+    {
+        k_traces<P><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, C, T, m.tab);
+    }
+    static void edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s)
+    {
+        k_edge<P><<<grid_for(m.nedge), BLOCK, 0, s>>>(m.nedge, m.edge_l, m.edge_r, m.edge_sd, m.edge_g, T, S, m.tab,
+                                                      m.gamma);
+    }
+    static void element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
+                        double dt, const double* dt_dev, double* Tn, hipStream_t s)
+    {
+        const double gm1 = m.gamma - 1.0;
+        dim3 g = grid_for(m.n);
+#define DG_ELEM(MODE, TR) k_element<P, MODE, TR><<<g, BLOCK, 0, s>>>(m.n, C, U0, out, S, m.geo, m.tab, gm1, dt, dt_dev, Tn)
+        switch (mode) {
+        case 0: DG_ELEM(0, false); break;
+        case 1: if (Tn) DG_ELEM(1, true); else DG_ELEM(1, false); break;
+        case 2: if (Tn) DG_ELEM(2, true); else DG_ELEM(2, false); break;
+        default: if (Tn) DG_ELEM(3, true); else DG_ELEM(3, false); break;
+        }
+#undef DG_ELEM
+    }
+    static void dt_partial(const MeshDev& m, const double* C, double* partial, hipStream_t s)
+    {
+        k_dt_partial<P><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, C, m.geo, m.gamma, partial);
+    }
+    static void project(const MeshDev& m, const double* uq, double* C, hipStream_t s)
+    {
+        k_project<P><<<grid_for(m.npad), BLOCK, 0, s>>>(m.n, m.npad, m.perm, uq, C, m.tab);
+    }
+    static void quad_points(const MeshDev& m, double* xy, hipStream_t s)
+    {
+        k_quad_points<P><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, m.perm, m.vtx, xy, m.tab);
+    }
+    static int offsets_match(const dgh::TableLayout& L)
+    {
+        using O = Ord<P>;
+        return O::NP == L.np && O::NQ == L.nq && O::NE == L.ne && O::PHI == L.phi && O::DRW == L.drw &&
+               O::DSW == L.dsw && O::PHS == L.phs && O::GW == L.gw && O::QW == L.qw && O::QR == L.qr && O::QS == L.qs;
+    }
+};
+
+extern template struct Launch<1>;
+extern template struct Launch<2>;
+extern template struct Launch<3>;
+extern template struct Launch<4>;
+extern template struct Launch<5>;
+
+}  // namespace dgk

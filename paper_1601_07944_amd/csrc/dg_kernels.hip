@@ -1,0 +1,100 @@
+// Order-independent kernels and the dispatch from a runtime order p to the
+// per-order instantiations (one translation unit per order).
+#include "dg_kernels.h"
+
+namespace dgk {
+
+__global__ __launch_bounds__(BLOCK) void k_dt_final(int nb, const double* __restrict__ partial, double cfl,
+                                                    double* __restrict__ dt)
+{
+    __shared__ double red[BLOCK];
+    double v = INFINITY;
+    for (int i = threadIdx.x; i < nb; i += BLOCK) v = fmin(v, partial[i]);
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dt[0] = red[0] < 0.0 ? __builtin_nan("") : cfl * red[0];
+}
+
+// ---------------------------------------------------------------- layout
+// user layout [N][4][NP] (user element order) <-> blocked internal layout
+__global__ __launch_bounds__(BLOCK) void k_pack(int n, int npad, int np, const int* __restrict__ perm,
+                                                const double* __restrict__ Cu, double* __restrict__ C)
+{
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= npad) return;
+    const int so = state_off(e, 4 * np);
+    if (e < n) {
+        const double* src = Cu + (size_t)perm[e] * 4 * np;
+        for (int x = 0; x < 4 * np; ++x) C[so + x * LANES] = src[x];
+    } else {
+        for (int x = 0; x < 4 * np; ++x) C[so + x * LANES] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_unpack(int n, int np, const int* __restrict__ perm,
+                                                  const double* __restrict__ C, double* __restrict__ Cu)
+{
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= n) return;
+    const int so = state_off(e, 4 * np);
+    double* dst = Cu + (size_t)perm[e] * 4 * np;
+    for (int x = 0; x < 4 * np; ++x) dst[x] = C[so + x * LANES];
+}
+
+#define DG_DISPATCH_P(p, CALL)                     \
+    switch (p) {                                   \
+    case 1: Launch<1>::CALL; break;                \
+    case 2: Launch<2>::CALL; break;                \
+    case 3: Launch<3>::CALL; break;                \
+    case 4: Launch<4>::CALL; break;                \
+    default: Launch<5>::CALL; break;               \
+    }
+
+void launch_traces(const MeshDev& m, const double* C, double* T, hipStream_t s) { DG_DISPATCH_P(m.p, traces(m, C, T, s)); }
+
+void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, edge_flux(m, T, S, s));
+}
+
+void launch_element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
+                    double dt, const double* dt_dev, double* Tn, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, element(m, mode, C, U0, out, S, dt, dt_dev, Tn, s));
+}
+
+int dt_partials(const MeshDev& m) { return (m.n + BLOCK - 1) / BLOCK; }
+
+void launch_dt(const MeshDev& m, const double* C, double cfl, double* partial, double* dt_dev, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, dt_partial(m, C, partial, s));
+    k_dt_final<<<1, BLOCK, 0, s>>>(dt_partials(m), partial, cfl, dt_dev);
+}
+
+void launch_pack(const MeshDev& m, const double* Cu, double* C, hipStream_t s)
+{
+    k_pack<<<grid_for(m.npad), BLOCK, 0, s>>>(m.n, m.npad, m.np, m.perm, Cu, C);
+}
+
+void launch_unpack(const MeshDev& m, const double* C, double* Cu, hipStream_t s)
+{
+    k_unpack<<<grid_for(m.n), BLOCK, 0, s>>>(m.n, m.np, m.perm, C, Cu);
+}
+
+void launch_project(const MeshDev& m, const double* uq, double* C, hipStream_t s) { DG_DISPATCH_P(m.p, project(m, uq, C, s)); }
+
+void launch_quad_points(const MeshDev& m, double* xy, hipStream_t s) { DG_DISPATCH_P(m.p, quad_points(m, xy, s)); }
+
+int table_offset_check(int p, const dgh::TableLayout& L)
+{
+    int ok = 0;
+    DG_DISPATCH_P(p, offsets_match(L) ? (void)(ok = 1) : (void)0);
+    return ok;
+}
+
+}  // namespace dgk

@@ -1,0 +1,6 @@
+// Kernels of order p = 3 (templates in dg_kernels.h).
+#include "dg_kernels.h"
+
+namespace dgk {
+template struct Launch<3>;
+}

@@ -1,0 +1,233 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+FP64 bar: relative L2 error <= 1e-11 over all coefficients in the user
+layout, and every element's coefficients within 1e-11 of the state's scale.
+Integer / layout work (pack, unpack, permutation) is compared bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_07944_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def case(msg):
+    print(f"[gpu case] {msg}", file=sys.stderr, flush=True)
+
+
+def torch_mod():
+    import torch
+
+    return torch
+
+
+def gpu_mesh(mesh, p):
+    from paper_1601_07944_amd import binding as B
+
+    return B.DGMesh.from_mesh(mesh, p)
+
+
+def to_dev(a):
+    torch = torch_mod()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def check_close(got, ref, tol=TOL):
+    err = rel_l2(got, ref)
+    scale = np.abs(ref).max()
+    worst = np.abs(got - ref).max() / scale
+    assert err <= tol and worst <= 10 * tol, (err, worst)
+    return err
+
+
+def gpu_rhs(mesh, p, C_user):
+    dm = gpu_mesh(mesh, p)
+    C = dm.pack(to_dev(C_user))
+    R = dm.rhs(C)
+    out = dm.unpack(R).cpu().numpy()
+    torch_mod().cuda.synchronize()
+    return out
+
+
+MESHES = {
+    "square23_j0.2": lambda: W.square_mesh(23, 1.0, 0.2, 5),  # 1058 elements: 16 full blocks + ragged tail
+    "delaunay517": lambda: W.delaunay_mesh(517, 6),  # 1034 elements, unstructured
+}
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("mname", sorted(MESHES))
+def test_rhs_random_state(p, mname):
+    mesh = MESHES[mname]()
+    orc = O.Oracle(mesh, p)
+    C = W.random_state(mesh.n_elem, orc.np, seed=10 + p)
+    case(f"dg_rhs p={p} mesh={mname} N={mesh.n_elem} seed={10 + p}")
+    got = gpu_rhs(mesh, p, C)
+    check_close(got, orc.rhs(C))
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_rhs_vortex_small_config(p):
+    mesh = W.square_mesh(16, 10.0, 0.1, 0)  # 512 triangles on [0,10]^2
+    orc = O.Oracle(mesh, p)
+    C = orc.project(W.isentropic_vortex)
+    case(f"dg_rhs vortex p={p} N=512")
+    check_close(gpu_rhs(mesh, p, C), orc.rhs(C))
+
+
+def test_rhs_full_size_p3_vortex():
+    # the 32,768-triangle p=3 vortex workload, whole state against the oracle
+    mesh = W.square_mesh(128, 10.0, 0.2, 1)
+    orc = O.Oracle(mesh, 3)
+    C = orc.project(W.isentropic_vortex)
+    case("dg_rhs vortex p=3 N=32768 (full size)")
+    check_close(gpu_rhs(mesh, 3, C), orc.rhs(C))
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (32, 7), (33, 8)])
+def test_rhs_edge_sizes(n, seed):
+    # 2 elements (every side borders the other), exactly 64, and 66 elements
+    mesh = W.square_mesh(1, 1.0, 0.0, 0) if n == 1 else W.delaunay_mesh(n, seed)
+    for p in (1, 4):
+        orc = O.Oracle(mesh, p)
+        C = W.random_state(mesh.n_elem, orc.np, seed=seed)
+        case(f"dg_rhs p={p} N={mesh.n_elem}")
+        check_close(gpu_rhs(mesh, p, C), orc.rhs(C))
+
+
+def test_pack_unpack_bit_exact():
+    torch = torch_mod()
+    mesh = W.delaunay_mesh(300, 2)
+    for p in (1, 5):
+        dm = gpu_mesh(mesh, p)
+        C = np.random.default_rng(p).normal(size=(mesh.n_elem, 4, dm.np))
+        case(f"dg_pack/dg_unpack p={p} N={mesh.n_elem}")
+        back = dm.unpack(dm.pack(to_dev(C))).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(back, C)
+
+
+@pytest.mark.parametrize("p", [1, 3, 5])
+def test_quad_points_and_projection(p):
+    mesh = W.square_mesh(9, 10.0, 0.2, 4)
+    orc = O.Oracle(mesh, p)
+    dm = gpu_mesh(mesh, p)
+    case(f"dg_quad_points/dg_project p={p}")
+    xy = dm.quad_points().cpu().numpy()
+    # the library may order the points of its rule differently: compare sets
+    xo = orc.quad_points()
+    a = np.sort(xy[..., 0] * 1e3 + xy[..., 1], axis=1)
+    b = np.sort(xo[..., 0] * 1e3 + xo[..., 1], axis=1)
+    assert np.abs(a - b).max() < 1e-10
+    u = W.isentropic_vortex(xy[..., 0], xy[..., 1])
+    Cg = dm.unpack(dm.project(to_dev(u))).cpu().numpy()
+    Co = orc.project(W.isentropic_vortex)
+    check_close(Cg, Co, 1e-13)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_max_dt(p):
+    mesh = W.delaunay_mesh(400, 9)
+    orc = O.Oracle(mesh, p)
+    C = orc.project(W.density_jump)
+    dm = gpu_mesh(mesh, p)
+    case(f"dg_max_dt p={p}")
+    _, dt = dm.max_dt(dm.pack(to_dev(C)), 0.3 / (2 * p + 1))
+    ref, rc = orc.max_dt(C, 0.3 / (2 * p + 1))
+    assert rc == 0 and abs(dt - ref) <= 1e-14 * ref
+
+
+def test_max_dt_nonphysical():
+    from paper_1601_07944_amd import binding as B
+
+    mesh = W.square_mesh(8, 1.0, 0.1, 1)
+    orc = O.Oracle(mesh, 2)
+    C = orc.project(W.smooth_density)
+    C[17, 0, 0] = -0.5
+    dm = gpu_mesh(mesh, 2)
+    case("dg_max_dt non-physical mean")
+    with pytest.raises(B.DGError) as ei:
+        dm.max_dt(dm.pack(to_dev(C)), 0.1)
+    assert ei.value.code == -7
+    dt_dev, _ = dm.max_dt(dm.pack(to_dev(C)), 0.1, to_host=False)
+    assert np.isnan(dt_dev.cpu().numpy()[0])
+
+
+def test_rk_step_vortex_to_t1_small_config():
+    # 512 triangles, p=1, isentropic vortex, SSP-RK3 with CFL 0.3/(2p+1) to t=1
+    torch = torch_mod()
+    mesh = W.square_mesh(16, 10.0, 0.1, 0)
+    p = 1
+    orc = O.Oracle(mesh, p)
+    Co = orc.project(W.isentropic_vortex)
+    dm = gpu_mesh(mesh, p)
+    Cg = dm.pack(to_dev(Co))
+    t, T, cfl = 0.0, 1.0, 0.3 / (2 * p + 1)
+    steps = 0
+    case("dg_rk_step vortex p=1 N=512 to t=1")
+    while t < T - 1e-14:
+        dto, _ = orc.max_dt(Co, cfl)
+        _, dtg = dm.max_dt(Cg, cfl)
+        assert abs(dtg - dto) <= 1e-12 * dto
+        dt = min(dto, T - t)
+        Co = orc.rk3_step(Co, dt)
+        dm.rk_step(Cg, dt)
+        t += dt
+        steps += 1
+    got = dm.unpack(Cg).cpu().numpy()
+    torch.cuda.synchronize()
+    assert steps > 100
+    check_close(got, Co)
+
+
+def test_rk_step_device_dt_matches_host_dt():
+    # the step length read from device memory (dg_max_dt output) gives the
+    # same result bit for bit as the host value
+    torch = torch_mod()
+    mesh = W.delaunay_mesh(700, 3)
+    orc = O.Oracle(mesh, 3)
+    C0 = orc.project(W.density_jump)
+    dm = gpu_mesh(mesh, 3)
+    case("dg_rk_step device dt vs host dt p=3")
+    A = dm.pack(to_dev(C0))
+    Bst = A.clone()
+    for _ in range(3):
+        dt_dev, dt = dm.max_dt(A, 0.3 / 7)
+        dm.rk_step(A, dt_dev=dt_dev)
+        dm.rk_step(Bst, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(A, Bst)
+    ref = C0
+    for _ in range(3):
+        dt, _ = orc.max_dt(ref, 0.3 / 7)
+        ref = orc.rk3_step(ref, dt)
+    check_close(dm.unpack(A).cpu().numpy(), ref)
+
+
+def test_bitwise_deterministic_across_streams():
+    torch = torch_mod()
+    mesh = W.delaunay_mesh(2000, 11)
+    p = 2
+    orc = O.Oracle(mesh, p)
+    C0 = W.random_state(mesh.n_elem, orc.np, seed=3)
+    dm = gpu_mesh(mesh, p)
+    case("determinism p=2 two streams")
+    C = dm.pack(to_dev(C0))
+    r1 = dm.rhs(C).clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ws2 = torch.empty(dm.info.ws_rhs, dtype=torch.uint8, device="cuda")
+        r2 = dm.rhs(C, ws=ws2, stream=s)
+    torch.cuda.synchronize()
+    assert torch.equal(r1, r2)
