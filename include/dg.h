@@ -155,6 +155,20 @@ int dg_max_dt(dg_mesh m, const double* C_dev, double cfl, double* dt_dev, double
 int dg_rk_step(dg_mesh m, double* C_dev, double dt, const double* dt_dev, dg_precision prec, void* ws_dev,
                void* stream);
 
+/* Organisation of the surface integral (Section "Surface Integration
+ * Kernel" discusses both):
+ *   DG_SURFACE_ELEMENTWISE (default): one fused kernel per right-hand side
+ *     or RK stage; every element evaluates the numerical flux on its own
+ *     three sides (each edge flux twice, as exact negatives of each other),
+ *     gathering the neighbour's coefficients; no edge temporaries;
+ *   DG_SURFACE_EDGEWISE: the paper's organisation: one work-item per edge
+ *     evaluates the flux once and stores it for both elements (per-side
+ *     slots, no atomics), then an element kernel combines; three kernels
+ *     per right-hand side.
+ * Both give the same discrete operator (equal up to rounding). */
+enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1 };
+int dg_set_surface_mode(dg_mesh m, int mode);
+
 /* Per-kernel timing (the paper's kernel runtime distribution, measured with
  * events around every launch).  dg_timing_enable(m, 1) makes every later
  * launch for this mesh record a pair of HIP events on its stream;
@@ -165,11 +179,12 @@ int dg_rk_step(dg_mesh m, double* C_dev, double dt, const double* dt_dev, dg_pre
  * per launch when on.  Not thread-safe for one mesh used from several
  * threads. */
 enum {
-    DG_KERNEL_TRACES = 0,   /* edge traces of a state */
-    DG_KERNEL_EDGE = 1,     /* numerical flux per edge into side slots */
-    DG_KERNEL_ELEMENT = 2,  /* volume + lift + inverse mass (+ RK stage) */
+    DG_KERNEL_TRACES = 0,   /* edge-wise path: edge traces of a state */
+    DG_KERNEL_EDGE = 1,     /* edge-wise path: numerical flux per edge into side slots */
+    DG_KERNEL_ELEMENT = 2,  /* edge-wise path: volume + lift + inverse mass (+ RK stage) */
     DG_KERNEL_DT = 3,       /* CFL reduction (both passes) */
-    DG_KERNEL_KINDS = 4
+    DG_KERNEL_STAGE = 4,    /* element-wise path: whole RHS (+ RK stage) in one kernel */
+    DG_KERNEL_KINDS = 5
 };
 int dg_timing_enable(dg_mesh m, int on);
 int dg_timing_read(dg_mesh m, double* ms, int64_t* count, int n);

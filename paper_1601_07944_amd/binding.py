@@ -43,6 +43,7 @@ EXPORTS = [
     "dg_rhs",
     "dg_max_dt",
     "dg_rk_step",
+    "dg_set_surface_mode",
     "dg_timing_enable",
     "dg_timing_read",
     "dg_reference_tables",
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.dg_rhs.argtypes = [_vp, _vp, _vp, i32, _vp, _vp]
     lib.dg_max_dt.argtypes = [_vp, _vp, ctypes.c_double, _vp, _dp, _vp, _vp]
     lib.dg_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _vp, i32, _vp, _vp]
+    lib.dg_set_surface_mode.argtypes = [_vp, i32]
     lib.dg_timing_enable.argtypes = [_vp, i32]
     lib.dg_timing_read.argtypes = [_vp, _dp, ctypes.POINTER(i64), i32]
     lib.dg_reference_tables.argtypes = [i32, _dp, i64]
@@ -264,16 +266,22 @@ class DGMesh:
                                    ctypes.byref(host) if to_host else None, _ptr(ws), _stream(stream)))
         return dt_dev, (host.value if to_host else None)
 
-    KERNELS = ("traces", "edge", "element", "dt")
+    KERNELS = ("traces", "edge", "element", "dt", "stage")
+    SURFACE_ELEMENTWISE = 0
+    SURFACE_EDGEWISE = 1
+
+    def set_surface_mode(self, mode: int):
+        _check(self._lib.dg_set_surface_mode(self._h, int(mode)))
 
     def timing(self, on: bool):
         _check(self._lib.dg_timing_enable(self._h, 1 if on else 0))
 
     def timing_read(self):
         """{kernel kind: (total ms, launches)} since the last read (waits)."""
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_int64 * 4)()
-        _check(self._lib.dg_timing_read(self._h, ms, cnt, 4))
+        nk = len(self.KERNELS)
+        ms = (ctypes.c_double * nk)()
+        cnt = (ctypes.c_int64 * nk)()
+        _check(self._lib.dg_timing_read(self._h, ms, cnt, nk))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
 
     def rk_step(self, C, dt=0.0, dt_dev=None, prec=DG_FP64, ws=None, stream=None):

@@ -22,6 +22,7 @@ struct dg_mesh_s {
     size_t off_T0 = 0, off_T1 = 0, off_S = 0, off_part = 0, off_u1 = 0, off_u2 = 0;
     std::vector<void*> allocs;
     // per-launch event timing (dg_timing_*)
+    int surface = DG_SURFACE_ELEMENTWISE;
     bool timing = false;
     struct Rec {
         int kind;
@@ -215,6 +216,27 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         eg[2 * (size_t)nedge + i] = egl[i];
     }
 
+    // per element side: neighbour (internal id), neighbour's side, own
+    // outward unit normal and half length (from the element's own vertices)
+    std::vector<int> snb((size_t)npad * 3, 0), sside((size_t)npad, 0);
+    std::vector<double> sg((size_t)npad * 9, 0.0);
+    for (int i = 0; i < N; ++i) {
+        const int u = perm[i];
+        const double* v = vxy + 6 * u;
+        const size_t b = (size_t)(i / 64) * 64;
+        int packed = 0;
+        for (int q = 0; q < 3; ++q) {
+            double dx = v[2 * ((q + 1) % 3)] - v[2 * q], dy = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
+            double len = std::sqrt(dx * dx + dy * dy);
+            snb[b * 3 + q * 64 + i % 64] = inv[nbr[3 * u + q]];
+            packed |= nbs[3 * u + q] << (2 * q);
+            sg[b * 9 + (3 * q + 0) * 64 + i % 64] = dy / len;
+            sg[b * 9 + (3 * q + 1) * 64 + i % 64] = -dx / len;
+            sg[b * 9 + (3 * q + 2) * 64 + i % 64] = 0.5 * len;
+        }
+        sside[b + i % 64] = packed;
+    }
+
     dgh::TableLayout lay;
     std::vector<double> tab = dgh::build_tables(p, &lay);
     if (!dgk::table_offset_check(p, lay) || lay.nq != nq)
@@ -234,11 +256,13 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         *dst = d;
         return DG_OK;
     };
-    void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg;
+    void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg, *d_snb, *d_sside, *d_sg;
     if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
         (rc = upload(vtx.data(), vtx.size() * 8, &d_vtx)) || (rc = upload(perm.data(), perm.size() * 4, &d_perm)) ||
         (rc = upload(el.data(), el.size() * 4, &d_el)) || (rc = upload(er.data(), er.size() * 4, &d_er)) ||
-        (rc = upload(sd.data(), sd.size() * 4, &d_sd)) || (rc = upload(eg.data(), eg.size() * 8, &d_eg))) {
+        (rc = upload(sd.data(), sd.size() * 4, &d_sd)) || (rc = upload(eg.data(), eg.size() * 8, &d_eg)) ||
+        (rc = upload(snb.data(), snb.size() * 4, &d_snb)) || (rc = upload(sside.data(), sside.size() * 4, &d_sside)) ||
+        (rc = upload(sg.data(), sg.size() * 8, &d_sg))) {
         std::string msg = g_err;
         dg_mesh_destroy(m);
         return fail(rc, "%s", msg.c_str());
@@ -260,6 +284,9 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.edge_r = (const int*)d_er;
     d.edge_sd = (const int*)d_sd;
     d.edge_g = (const double*)d_eg;
+    d.side_nb = (const int*)d_snb;
+    d.side_q = (const int*)d_sside;
+    d.side_g = (const double*)d_sg;
     m->lay = lay;
 
     const size_t state = align256((size_t)npad * 4 * np * 8);
@@ -385,6 +412,10 @@ int dg_rhs(dg_mesh m, const double* C, double* R, dg_precision prec, void* ws, v
     double* T = (double*)(w + m->off_T0);
     double* S = (double*)(w + m->off_S);
     hipStream_t s = (hipStream_t)stream;
+    if (m->surface == DG_SURFACE_ELEMENTWISE) {
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(m->dev, 0, C, nullptr, R, 0.0, nullptr, s); });
+        return check_launch("dg_rhs");
+    }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s); });
     timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(m->dev, T, S, s); });
     timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(m->dev, 0, C, nullptr, R, S, 0.0, nullptr, nullptr, s); });
@@ -417,6 +448,12 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
     double* u2 = (double*)(w + m->off_u2);
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
+    if (m->surface == DG_SURFACE_ELEMENTWISE) {
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, C, nullptr, u1, dt, dt_dev, s); });
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, u1, C, u2, dt, dt_dev, s); });
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, u2, C, C, dt, dt_dev, s); });
+        return check_launch("dg_rk_step");
+    }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s); });
     timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, T0, S, s); });
     timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 1, C, nullptr, u1, S, dt, dt_dev, T1, s); });
@@ -425,6 +462,15 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
     timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, T0, S, s); });
     timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 3, u2, C, C, S, dt, dt_dev, nullptr, s); });
     return check_launch("dg_rk_step");
+}
+
+int dg_set_surface_mode(dg_mesh m, int mode)
+{
+    if (!m) return fail(DG_EINVAL, "null mesh");
+    if (mode != DG_SURFACE_ELEMENTWISE && mode != DG_SURFACE_EDGEWISE)
+        return fail(DG_EINVAL, "unknown surface mode %d", mode);
+    m->surface = mode;
+    return ok();
 }
 
 int dg_timing_enable(dg_mesh m, int on)

@@ -44,6 +44,10 @@ struct MeshDev {
     const int* edge_r = nullptr;      // [nedge] right element
     const int* edge_sd = nullptr;     // [nedge] side_l | side_r << 2
     const double* edge_g = nullptr;   // SoA [3][nedge]: unit normal (left -> right) x, y; half length
+    // per element side (element-wise surface integration), block-major:
+    const int* side_nb = nullptr;     // [blk][3][64] neighbour across side q (internal id)
+    const int* side_q = nullptr;      // [blk][64] neighbour's sides, 2 bits per side
+    const double* side_g = nullptr;   // [blk][9][64] outward unit normal x, y and half length per side
 };
 
 // Launchers (dg_kernels.hip).  All asynchronous on `s`.
@@ -53,6 +57,10 @@ void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t 
 // when Tnext != nullptr the traces of `out` are written to it.
 void launch_element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
                     double dt, const double* dt_dev, double* Tnext, hipStream_t s);
+// fused right-hand side / SSP-RK3 stage (element-wise surface integral);
+// mode as for launch_element
+void launch_stage(const MeshDev& m, int mode, const double* C, const double* U0, double* out, double dt,
+                  const double* dt_dev, hipStream_t s);
 void launch_dt(const MeshDev& m, const double* C, double cfl, double* partial, double* dt_dev, hipStream_t s);
 int dt_partials(const MeshDev& m);
 void launch_pack(const MeshDev& m, const double* Cu, double* C, hipStream_t s);

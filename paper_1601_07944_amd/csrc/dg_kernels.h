@@ -160,17 +160,25 @@ __global__ __launch_bounds__(BLOCK) void k_edge(int nedge, const int* __restrict
 }
 
 // ---------------------------------------------------------------- elements
+// The grid covers the padded element count: padding lanes write zeros, so
+// every state this kernel produces has a defined (zero) padding.
 template <int P, int MODE, bool TRACE>
-__global__ __launch_bounds__(BLOCK) void k_element(int n, const double* __restrict__ C, const double* U0, double* out,
-                                                   const double* __restrict__ S, const double* __restrict__ geo,
-                                                   const double* __restrict__ tab, double gm1, double dt,
-                                                   const double* __restrict__ dt_dev, double* __restrict__ Tn)
+__global__ __launch_bounds__(BLOCK) void k_element(int n, int npad, const double* __restrict__ C, const double* U0,
+                                                   double* out, const double* __restrict__ S,
+                                                   const double* __restrict__ geo, const double* __restrict__ tab,
+                                                   double gm1, double dt, const double* __restrict__ dt_dev,
+                                                   double* __restrict__ Tn)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
     const int e = blockIdx.x * BLOCK + threadIdx.x;
-    if (e >= n) return;
+    if (e >= npad) return;
     const int so = state_off(e, 4 * NP);
+    if (e >= n) {
+#pragma unroll
+        for (int x = 0; x < 4 * NP; ++x) out[so + x * LANES] = 0.0;
+        return;
+    }
     const double* g = geo + state_off(e, 6);
     const double a00 = g[0], a01 = g[LANES], a10 = g[2 * LANES], a11 = g[3 * LANES], idet = g[4 * LANES];
 
@@ -229,6 +237,15 @@ __global__ __launch_bounds__(BLOCK) void k_element(int n, const double* __restri
             for (int j = 0; j < NP; ++j) out[so + (m * NP + j) * LANES] = idet * acc[m][j];
     } else {
         const double h = dt_dev ? dt_dev[0] : dt;
+        // stage-0 values are all loaded before the first store: in stage 3
+        // U0 and out are the same array
+        double u0[4][NP];
+        if constexpr (MODE != 1) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) u0[m][j] = U0[so + (m * NP + j) * LANES];
+        }
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -238,14 +255,183 @@ __global__ __launch_bounds__(BLOCK) void k_element(int n, const double* __restri
                 if constexpr (MODE == 1) {
                     v = c[m][j] + h * L;
                 } else if constexpr (MODE == 2) {
-                    v = 0.75 * U0[so + (m * NP + j) * LANES] + 0.25 * (c[m][j] + h * L);
+                    v = 0.75 * u0[m][j] + 0.25 * (c[m][j] + h * L);
                 } else {
-                    v = (1.0 / 3.0) * U0[so + (m * NP + j) * LANES] + (2.0 / 3.0) * (c[m][j] + h * L);
+                    v = (1.0 / 3.0) * u0[m][j] + (2.0 / 3.0) * (c[m][j] + h * L);
                 }
-                out[so + (m * NP + j) * LANES] = v;
                 c[m][j] = v;
             }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) out[so + (m * NP + j) * LANES] = c[m][j];
         if constexpr (TRACE) store_traces<P>(c, tab, Tn + to);
+    }
+}
+
+// ---------------------------------------------------------------- fused stage
+// Element-wise surface integration: each work-item evaluates the numerical
+// flux of its own three sides (so every edge flux is computed twice, once
+// from each side; LLF is written so the two evaluations are exact
+// negatives and conservation is kept bitwise), gathering the neighbour's
+// trace from the neighbour's coefficients.  One kernel then does the whole
+// right-hand side of eq. (2ddg0) and the SSP-RK3 stage update, with no edge
+// temporaries in memory.  The neighbour's side differs per lane, so the side
+// tables it needs are read from LDS (odd stride between sides: the three
+// possible side addresses fall in different banks); tables indexed by the
+// element's own side or volume point are uniform and go through scalar loads.
+
+// Workgroups are dealt round-robin to the 8 XCDs; remap them so that each
+// XCD works on one contiguous range of the space-filling-curve order and
+// neighbour gathers stay in that XCD's L2.
+__device__ __forceinline__ int xcd_block(int bid, int nblk_grid)
+{
+    const int chunk = nblk_grid >> 3;  // grid is padded to a multiple of 8
+    return (bid & 7) * chunk + (bid >> 3);
+}
+
+template <int P, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* __restrict__ C, const double* U0,
+                                                 double* out, const double* __restrict__ geo,
+                                                 const int* __restrict__ snb, const int* __restrict__ sside,
+                                                 const double* __restrict__ sgeo, const double* __restrict__ tab,
+                                                 double gamma, double dt, const double* __restrict__ dt_dev)
+{
+    using O = Ord<P>;
+    constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
+    constexpr int SS = (NE * NP) | 1;
+    __shared__ double phs[3 * SS];
+    for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) phs[(i / (NE * NP)) * SS + i % (NE * NP)] = tab[O::PHS + i];
+    __syncthreads();
+
+    const int e = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (e >= npad) return;
+    const int so = state_off(e, 4 * NP);
+    if (e >= n) {
+#pragma unroll
+        for (int x = 0; x < 4 * NP; ++x) out[so + x * LANES] = 0.0;
+        return;
+    }
+    const double gm1 = gamma - 1.0;
+    const double* g = geo + state_off(e, 6);
+    const double a00 = g[0], a01 = g[LANES], a10 = g[2 * LANES], a11 = g[3 * LANES], idet = g[4 * LANES];
+
+    double c[4][NP];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) c[m][j] = C[so + (m * NP + j) * LANES];
+
+    double acc[4][NP];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) acc[m][j] = 0.0;
+
+    // surface integral, eq. (surface): the element's own three sides
+    const int sides = sside[state_off(e, 1)];
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        const int nb = snb[state_off(e, 3) + q * LANES];
+        const int qn = (sides >> (2 * q)) & 3;
+        const int go = state_off(e, 9) + 3 * q * LANES;
+        const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
+        // neighbour trace at its side qn, at the reversed edge points
+        double UR[NE][4];
+#pragma unroll
+        for (int k = 0; k < NE; ++k)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) UR[k][m] = 0.0;
+        const int nbo = state_off(nb, 4 * NP);
+        const double* tq = phs + qn * SS;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            double cv[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) cv[m] = C[nbo + (m * NP + j) * LANES];
+#pragma unroll
+            for (int k = 0; k < NE; ++k) {
+                const double t = tq[(NE - 1 - k) * NP + j];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) UR[k][m] = fma(t, cv[m], UR[k][m]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const double* tl = tab + O::PHS + (q * NE + k) * NP;
+            double UL[4], F[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                double u = 0.0;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) u = fma(tl[j], c[m][j], u);
+                UL[m] = u;
+            }
+            llf(gamma, gm1, UL, UR[k], nx, ny, F);
+            const double w = -hl * tab[O::GW + k];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) F[m] *= w;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) acc[m][j] = fma(tl[j], F[m], acc[m][j]);
+        }
+    }
+
+    // volume integral, eq. (volume)
+#pragma unroll 1
+    for (int k = 0; k < NQ; ++k) {
+        double U[4], Fx[4], Fy[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double u = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) u = fma(tab[O::PHI + k * NP + j], c[m][j], u);
+            U[m] = u;
+        }
+        euler_flux(gm1, U, Fx, Fy);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double gr = a00 * Fx[m] + a01 * Fy[m];
+            const double gs = a10 * Fx[m] + a11 * Fy[m];
+#pragma unroll
+            for (int j = 0; j < NP; ++j)
+                acc[m][j] = fma(tab[O::DRW + k * NP + j], gr, fma(tab[O::DSW + k * NP + j], gs, acc[m][j]));
+        }
+    }
+
+    // inverse mass matrix 1/det J, then the plain RHS or the SSP-RK3 stage
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) out[so + (m * NP + j) * LANES] = idet * acc[m][j];
+    } else {
+        const double h = dt_dev ? dt_dev[0] : dt;
+        double u0[4][NP];
+        if constexpr (MODE != 1) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) u0[m][j] = U0[so + (m * NP + j) * LANES];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const double L = idet * acc[m][j];
+                if constexpr (MODE == 1) {
+                    c[m][j] = c[m][j] + h * L;
+                } else if constexpr (MODE == 2) {
+                    c[m][j] = 0.75 * u0[m][j] + 0.25 * (c[m][j] + h * L);
+                } else {
+                    c[m][j] = (1.0 / 3.0) * u0[m][j] + (2.0 / 3.0) * (c[m][j] + h * L);
+                }
+            }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) out[so + (m * NP + j) * LANES] = c[m][j];
     }
 }
 
@@ -348,8 +534,9 @@ struct Launch {
                         double dt, const double* dt_dev, double* Tn, hipStream_t s)
     {
         const double gm1 = m.gamma - 1.0;
-        dim3 g = grid_for(m.n);
-#define DG_ELEM(MODE, TR) k_element<P, MODE, TR><<<g, BLOCK, 0, s>>>(m.n, C, U0, out, S, m.geo, m.tab, gm1, dt, dt_dev, Tn)
+        dim3 g = grid_for(m.npad);
+#define DG_ELEM(MODE, TR) \
+    k_element<P, MODE, TR><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, S, m.geo, m.tab, gm1, dt, dt_dev, Tn)
         switch (mode) {
         case 0: DG_ELEM(0, false); break;
         case 1: if (Tn) DG_ELEM(1, true); else DG_ELEM(1, false); break;
@@ -357,6 +544,22 @@ struct Launch {
         default: if (Tn) DG_ELEM(3, true); else DG_ELEM(3, false); break;
         }
 #undef DG_ELEM
+    }
+    static void stage(const MeshDev& m, int mode, const double* C, const double* U0, double* out, double dt,
+                      const double* dt_dev, hipStream_t s)
+    {
+        const int nb = (m.npad + BLOCK - 1) / BLOCK;
+        dim3 g((nb + 7) / 8 * 8);
+#define DG_STAGE(MODE)                                                                                         \
+    k_stage<P, MODE><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, m.tab, \
+                                         m.gamma, dt, dt_dev)
+        switch (mode) {
+        case 0: DG_STAGE(0); break;
+        case 1: DG_STAGE(1); break;
+        case 2: DG_STAGE(2); break;
+        default: DG_STAGE(3); break;
+        }
+#undef DG_STAGE
     }
     static void dt_partial(const MeshDev& m, const double* C, double* partial, hipStream_t s)
     {

@@ -68,6 +68,12 @@ void launch_element(const MeshDev& m, int mode, const double* C, const double* U
     DG_DISPATCH_P(m.p, element(m, mode, C, U0, out, S, dt, dt_dev, Tn, s));
 }
 
+void launch_stage(const MeshDev& m, int mode, const double* C, const double* U0, double* out, double dt,
+                  const double* dt_dev, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, stage(m, mode, C, U0, out, dt, dt_dev, s));
+}
+
 int dt_partials(const MeshDev& m) { return (m.n + BLOCK - 1) / BLOCK; }
 
 void launch_dt(const MeshDev& m, const double* C, double cfl, double* partial, double* dt_dev, hipStream_t s)

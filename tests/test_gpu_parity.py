@@ -27,10 +27,16 @@ def torch_mod():
     return torch
 
 
-def gpu_mesh(mesh, p):
+ELEMENTWISE, EDGEWISE = 0, 1
+SURFACE = {"elementwise": ELEMENTWISE, "edgewise": EDGEWISE}
+
+
+def gpu_mesh(mesh, p, surface=ELEMENTWISE):
     from paper_1601_07944_amd import binding as B
 
-    return B.DGMesh.from_mesh(mesh, p)
+    dm = B.DGMesh.from_mesh(mesh, p)
+    dm.set_surface_mode(surface)
+    return dm
 
 
 def to_dev(a):
@@ -50,8 +56,8 @@ def check_close(got, ref, tol=TOL):
     return err
 
 
-def gpu_rhs(mesh, p, C_user):
-    dm = gpu_mesh(mesh, p)
+def gpu_rhs(mesh, p, C_user, surface=ELEMENTWISE):
+    dm = gpu_mesh(mesh, p, surface)
     C = dm.pack(to_dev(C_user))
     R = dm.rhs(C)
     out = dm.unpack(R).cpu().numpy()
@@ -65,14 +71,15 @@ MESHES = {
 }
 
 
+@pytest.mark.parametrize("surface", sorted(SURFACE))
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("mname", sorted(MESHES))
-def test_rhs_random_state(p, mname):
+def test_rhs_random_state(p, mname, surface):
     mesh = MESHES[mname]()
     orc = O.Oracle(mesh, p)
     C = W.random_state(mesh.n_elem, orc.np, seed=10 + p)
-    case(f"dg_rhs p={p} mesh={mname} N={mesh.n_elem} seed={10 + p}")
-    got = gpu_rhs(mesh, p, C)
+    case(f"dg_rhs p={p} mesh={mname} N={mesh.n_elem} seed={10 + p} surface={surface}")
+    got = gpu_rhs(mesh, p, C, SURFACE[surface])
     check_close(got, orc.rhs(C))
 
 
@@ -94,15 +101,18 @@ def test_rhs_full_size_p3_vortex():
     check_close(gpu_rhs(mesh, 3, C), orc.rhs(C))
 
 
-@pytest.mark.parametrize("n,seed", [(1, 0), (32, 7), (33, 8)])
-def test_rhs_edge_sizes(n, seed):
-    # 2 elements (every side borders the other), exactly 64, and 66 elements
+@pytest.mark.parametrize("surface", sorted(SURFACE))
+@pytest.mark.parametrize("n,seed", [(1, 0), (32, 7), (33, 8), (1100, 9)])
+def test_rhs_edge_sizes(n, seed, surface):
+    # 2 elements (every side borders the other), exactly 64, 66, and 2200
+    # elements (8 full 256-element workgroups + a ragged one: exercises the
+    # XCD remap with a grid padded to a multiple of 8)
     mesh = W.square_mesh(1, 1.0, 0.0, 0) if n == 1 else W.delaunay_mesh(n, seed)
     for p in (1, 4):
         orc = O.Oracle(mesh, p)
         C = W.random_state(mesh.n_elem, orc.np, seed=seed)
-        case(f"dg_rhs p={p} N={mesh.n_elem}")
-        check_close(gpu_rhs(mesh, p, C), orc.rhs(C))
+        case(f"dg_rhs p={p} N={mesh.n_elem} surface={surface}")
+        check_close(gpu_rhs(mesh, p, C, SURFACE[surface]), orc.rhs(C))
 
 
 def test_pack_unpack_bit_exact():
@@ -163,18 +173,19 @@ def test_max_dt_nonphysical():
     assert np.isnan(dt_dev.cpu().numpy()[0])
 
 
-def test_rk_step_vortex_to_t1_small_config():
+@pytest.mark.parametrize("surface", sorted(SURFACE))
+def test_rk_step_vortex_to_t1_small_config(surface):
     # 512 triangles, p=1, isentropic vortex, SSP-RK3 with CFL 0.3/(2p+1) to t=1
     torch = torch_mod()
     mesh = W.square_mesh(16, 10.0, 0.1, 0)
     p = 1
     orc = O.Oracle(mesh, p)
     Co = orc.project(W.isentropic_vortex)
-    dm = gpu_mesh(mesh, p)
+    dm = gpu_mesh(mesh, p, SURFACE[surface])
     Cg = dm.pack(to_dev(Co))
     t, T, cfl = 0.0, 1.0, 0.3 / (2 * p + 1)
     steps = 0
-    case("dg_rk_step vortex p=1 N=512 to t=1")
+    case(f"dg_rk_step vortex p=1 N=512 to t=1 surface={surface}")
     while t < T - 1e-14:
         dto, _ = orc.max_dt(Co, cfl)
         _, dtg = dm.max_dt(Cg, cfl)
@@ -231,3 +242,40 @@ def test_bitwise_deterministic_across_streams():
         r2 = dm.rhs(C, ws=ws2, stream=s)
     torch.cuda.synchronize()
     assert torch.equal(r1, r2)
+
+
+@pytest.mark.parametrize("p", [1, 3, 5])
+def test_surface_strategies_agree_and_conserve(p):
+    # the two surface organisations give the same operator up to rounding;
+    # element means change only through edge fluxes that cancel pairwise
+    torch = torch_mod()
+    mesh = W.delaunay_mesh(1500, 21)
+    orc = O.Oracle(mesh, p)
+    C = W.random_state(mesh.n_elem, orc.np, seed=5)
+    case(f"surface strategies p={p}")
+    a = gpu_rhs(mesh, p, C, ELEMENTWISE)
+    b = gpu_rhs(mesh, p, C, EDGEWISE)
+    check_close(a, b, 1e-13)
+    det = orc.det()
+    for R in (a, b):
+        terms = det[:, None] * R[:, :, 0]
+        assert np.all(np.abs(terms.sum(0)) < 1e-13 * np.abs(terms).sum(0))
+
+
+def test_full_size_p3_step_sampled():
+    # the benchmark's launch configuration: 32,768 triangles, p=3, one
+    # SSP-RK3 step with dt from dg_max_dt on the device; whole state checked
+    torch = torch_mod()
+    mesh = W.square_mesh(128, 10.0, 0.2, 1)
+    orc = O.Oracle(mesh, 3)
+    C0 = orc.project(W.isentropic_vortex)
+    dm = gpu_mesh(mesh, 3)
+    case("bench configuration: one step p=3 N=32768")
+    Cg = dm.pack(to_dev(C0))
+    ws = dm.workspace("step")
+    dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    dm.max_dt(Cg, 0.3 / 7, dt_dev=dt_dev, to_host=False, ws=ws)
+    dm.rk_step(Cg, dt_dev=dt_dev, ws=ws)
+    got = dm.unpack(Cg).cpu().numpy()
+    dt, _ = orc.max_dt(C0, 0.3 / 7)
+    check_close(got, orc.rk3_step(C0, dt))
