@@ -145,9 +145,12 @@ def main():
     cfl = 0.3 / (2 * p + 1)
     dof = dm.n * dm.np * 4
 
+    def step_prec(state, prec):
+        dm.max_dt(state, cfl, dt_dev=dt_dev, to_host=False, ws=ws)
+        dm.rk_step(state, dt_dev=dt_dev, prec=prec, ws=ws)
+
     def step():
-        dm.max_dt(C, cfl, dt_dev=dt_dev, to_host=False, ws=ws)
-        dm.rk_step(C, dt_dev=dt_dev, ws=ws)
+        step_prec(C, B.DG_FP64)
 
     for _ in range(args.warmup):
         step()
@@ -213,6 +216,25 @@ def main():
     ach = algorithmic_bytes_stage_kernel(dm.n, dm.np, 2.0 / 3.0) / (st_ms / st_n * 1e-3) / 1e9
     traffic = load_traffic("stage")
 
+    # mixed precision (FP32 contractions/fluxes, FP64 means, update, dt):
+    # same steps, and its error after K steps against the FP64 path
+    C64 = C.clone()
+    Cmx = C.clone()
+    for _ in range(5):
+        step_prec(Cmx, B.DG_MIXED)
+    Cmx.copy_(C64)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step_prec(Cmx, B.DG_MIXED)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step_mixed = e0.elapsed_time(e1) / args.steps
+    for _ in range(args.steps):
+        step_prec(C64, B.DG_FP64)
+    torch.cuda.synchronize()
+    mixed_err = float(torch.linalg.norm(Cmx - C64) / torch.linalg.norm(C64))
+
     # the paper's edge-wise organisation (3 kernels per RHS), same steps
     dm.set_surface_mode(dm.SURFACE_EDGEWISE)
     for _ in range(5):
@@ -261,7 +283,13 @@ def main():
         "surface_edgewise": {"ms_per_step": ms_step_edge, "value": dof * 3 / (ms_step_edge * 1e-3)},
         "wall_s_timed_region": wall,
         "rhs_only": {"value": dof / (ms_rhs * 1e-3), "unit": "DOF-updates/s", "ms_per_call": ms_rhs},
-        "mixed": None,
+        "mixed": {
+            "value": dof * 3 / (ms_step_mixed * 1e-3),
+            "ms_per_step": ms_step_mixed,
+            "speedup_vs_fp64": ms_step / ms_step_mixed,
+            "rel_l2_vs_fp64_after_steps": mixed_err,
+            "steps": args.steps,
+        },
         "adjoint_forward_ratio": None,
     }
     if not args.no_cpu_baseline:

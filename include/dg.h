@@ -72,7 +72,9 @@ typedef enum {
 
 typedef enum {
     DG_FP64 = 0,  /* every step in double precision */
-    DG_MIXED = 1  /* reserved: FP32 contractions/flux, FP64 stage update */
+    DG_MIXED = 1  /* contractions, traces, fluxes and the lift of modes >= 2 in
+                     FP32; the mean mode, 1/det J, the stage update, the state
+                     and the CFL reduction in FP64 (element-wise mode only) */
 } dg_precision;
 
 typedef struct {
@@ -135,7 +137,8 @@ int dg_unpack(dg_mesh m, const double* C_dev, double* C_user_dev, void* stream);
 
 /* Right-hand side of eq. (2ddg0): R = M^{-1} (volume - surface), internal
  * layout in and out (C_dev and R_dev must not overlap).  ws_dev: ws_rhs
- * bytes.  prec must be DG_FP64 (DG_MIXED: DG_EUNSUPPORTED in this build). */
+ * bytes.  prec: DG_FP64 or DG_MIXED (DG_MIXED needs the element-wise
+ * surface mode, else DG_EUNSUPPORTED). */
 int dg_rhs(dg_mesh m, const double* C_dev, double* R_dev, dg_precision prec, void* ws_dev, void* stream);
 
 /* Stable time step (the paper computes one per step on the device): writes

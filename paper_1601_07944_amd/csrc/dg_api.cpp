@@ -256,8 +256,10 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         *dst = d;
         return DG_OK;
     };
+    std::vector<float> tab32(tab.begin(), tab.end());
+    void *d_tab32;
     void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg, *d_snb, *d_sside, *d_sg;
-    if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
+    if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(tab32.data(), tab32.size() * 4, &d_tab32)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
         (rc = upload(vtx.data(), vtx.size() * 8, &d_vtx)) || (rc = upload(perm.data(), perm.size() * 4, &d_perm)) ||
         (rc = upload(el.data(), el.size() * 4, &d_el)) || (rc = upload(er.data(), er.size() * 4, &d_er)) ||
         (rc = upload(sd.data(), sd.size() * 4, &d_sd)) || (rc = upload(eg.data(), eg.size() * 8, &d_eg)) ||
@@ -277,6 +279,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.nedge = nedge;
     d.gamma = gamma;
     d.tab = (const double*)d_tab;
+    d.tab32 = (const float*)d_tab32;
     d.geo = (const double*)d_geo;
     d.vtx = (const double*)d_vtx;
     d.perm = (const int*)d_perm;
@@ -407,13 +410,16 @@ int dg_unpack(dg_mesh m, const double* C, double* Cu, void* stream)
 int dg_rhs(dg_mesh m, const double* C, double* R, dg_precision prec, void* ws, void* stream)
 {
     if (!m || !C || !R || !ws) return fail(DG_EINVAL, "null argument");
-    if (prec != DG_FP64) return fail(prec == DG_MIXED ? DG_EUNSUPPORTED : DG_EINVAL, "precision %d not available", prec);
+    if (prec != DG_FP64 && prec != DG_MIXED) return fail(DG_EINVAL, "unknown precision %d", prec);
+    if (prec == DG_MIXED && m->surface != DG_SURFACE_ELEMENTWISE)
+        return fail(DG_EUNSUPPORTED, "DG_MIXED needs the element-wise surface mode");
     char* w = (char*)ws;
     double* T = (double*)(w + m->off_T0);
     double* S = (double*)(w + m->off_S);
     hipStream_t s = (hipStream_t)stream;
     if (m->surface == DG_SURFACE_ELEMENTWISE) {
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(m->dev, 0, C, nullptr, R, 0.0, nullptr, s); });
+        const bool mixed = prec == DG_MIXED;
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(m->dev, 0, mixed, C, nullptr, R, 0.0, nullptr, s); });
         return check_launch("dg_rhs");
     }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s); });
@@ -439,7 +445,9 @@ int dg_max_dt(dg_mesh m, const double* C, double cfl, double* dt_dev, double* dt
 int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precision prec, void* ws, void* stream)
 {
     if (!m || !C || !ws) return fail(DG_EINVAL, "null argument");
-    if (prec != DG_FP64) return fail(prec == DG_MIXED ? DG_EUNSUPPORTED : DG_EINVAL, "precision %d not available", prec);
+    if (prec != DG_FP64 && prec != DG_MIXED) return fail(DG_EINVAL, "unknown precision %d", prec);
+    if (prec == DG_MIXED && m->surface != DG_SURFACE_ELEMENTWISE)
+        return fail(DG_EUNSUPPORTED, "DG_MIXED needs the element-wise surface mode");
     char* w = (char*)ws;
     double* T0 = (double*)(w + m->off_T0);
     double* T1 = (double*)(w + m->off_T1);
@@ -449,9 +457,10 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
     if (m->surface == DG_SURFACE_ELEMENTWISE) {
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, C, nullptr, u1, dt, dt_dev, s); });
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, u1, C, u2, dt, dt_dev, s); });
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, u2, C, C, dt, dt_dev, s); });
+        const bool mx = prec == DG_MIXED;
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, dt, dt_dev, s); });
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, mx, u1, C, u2, dt, dt_dev, s); });
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, mx, u2, nullptr, C, dt, dt_dev, s); });
         return check_launch("dg_rk_step");
     }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s); });

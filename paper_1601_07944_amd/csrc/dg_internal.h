@@ -37,6 +37,7 @@ struct MeshDev {
     int nedge = 0;
     double gamma = 1.4;
     const double* tab = nullptr;      // reference tables (TableLayout)
+    const float* tab32 = nullptr;     // the same tables rounded to FP32 (mixed precision)
     const double* geo = nullptr;      // [blk][6][64]: adj00 adj01 adj10 adj11 1/detJ r_in
     const double* vtx = nullptr;      // [npad][6] vertices (internal order), setup only
     const int* perm = nullptr;        // internal -> user element id
@@ -58,8 +59,9 @@ void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t 
 void launch_element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
                     double dt, const double* dt_dev, double* Tnext, hipStream_t s);
 // fused right-hand side / SSP-RK3 stage (element-wise surface integral);
-// mode as for launch_element
-void launch_stage(const MeshDev& m, int mode, const double* C, const double* U0, double* out, double dt,
+// mode as for launch_element, except that mode 3 updates `out` in place
+// (it is the stage-0 state) and U0 must be nullptr
+void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out, double dt,
                   const double* dt_dev, hipStream_t s);
 void launch_dt(const MeshDev& m, const double* C, double cfl, double* partial, double* dt_dev, hipStream_t s);
 int dt_partials(const MeshDev& m);

@@ -53,11 +53,13 @@ __device__ __forceinline__ int state_off(int e, int nfield) { return (e >> 6) * 
 
 // ---------------------------------------------------------------- physics
 // Euler flux eq. (euler) at one point; p = (gamma-1)(E - rho |v|^2 / 2).
-__device__ __forceinline__ void euler_flux(double gm1, const double U[4], double Fx[4], double Fy[4])
+// T is the arithmetic type (double, or float in the mixed-precision form).
+template <typename T>
+__device__ __forceinline__ void euler_flux(T gm1, const T U[4], T Fx[4], T Fy[4])
 {
-    const double ri = 1.0 / U[0];
-    const double u = U[1] * ri, v = U[2] * ri;
-    const double p = gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
+    const T ri = T(1) / U[0];
+    const T u = U[1] * ri, v = U[2] * ri;
+    const T p = gm1 * (U[3] - T(0.5) * (U[1] * u + U[2] * v));
     Fx[0] = U[1];
     Fx[1] = U[1] * u + p;
     Fx[2] = U[2] * u;
@@ -72,21 +74,21 @@ __device__ __forceinline__ void euler_flux(double gm1, const double U[4], double
 // Fn = (F(UL).n + F(UR).n)/2 - lambda/2 (UR - UL),
 // lambda = max(|vL.n| + cL, |vR.n| + cR).  Exchanging L and R and negating n
 // negates Fn bitwise.
-__device__ __forceinline__ void llf(double gamma, double gm1, const double UL[4], const double UR[4], double nx,
-                                    double ny, double Fn[4])
+template <typename T>
+__device__ __forceinline__ void llf(T gamma, T gm1, const T UL[4], const T UR[4], T nx, T ny, T Fn[4])
 {
-    const double riL = 1.0 / UL[0], riR = 1.0 / UR[0];
-    const double uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
-    const double pL = gm1 * (UL[3] - 0.5 * (UL[1] * uL + UL[2] * vL));
-    const double pR = gm1 * (UR[3] - 0.5 * (UR[1] * uR + UR[2] * vR));
-    const double vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
-    const double lamL = fabs(vnL) + sqrt(gamma * pL * riL);
-    const double lamR = fabs(vnR) + sqrt(gamma * pR * riR);
-    const double lam = fmax(lamL, lamR);
-    const double fL[4] = {UL[0] * vnL, UL[1] * vnL + pL * nx, UL[2] * vnL + pL * ny, (UL[3] + pL) * vnL};
-    const double fR[4] = {UR[0] * vnR, UR[1] * vnR + pR * nx, UR[2] * vnR + pR * ny, (UR[3] + pR) * vnR};
+    const T riL = T(1) / UL[0], riR = T(1) / UR[0];
+    const T uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
+    const T pL = gm1 * (UL[3] - T(0.5) * (UL[1] * uL + UL[2] * vL));
+    const T pR = gm1 * (UR[3] - T(0.5) * (UR[1] * uR + UR[2] * vR));
+    const T vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
+    const T lamL = fabs(vnL) + sqrt(gamma * pL * riL);
+    const T lamR = fabs(vnR) + sqrt(gamma * pR * riR);
+    const T lam = fmax(lamL, lamR);
+    const T fL[4] = {UL[0] * vnL, UL[1] * vnL + pL * nx, UL[2] * vnL + pL * ny, (UL[3] + pL) * vnL};
+    const T fR[4] = {UR[0] * vnR, UR[1] * vnR + pR * nx, UR[2] * vnR + pR * ny, (UR[3] + pR) * vnR};
 #pragma unroll
-    for (int m = 0; m < 4; ++m) Fn[m] = 0.5 * (fL[m] + fR[m]) - 0.5 * lam * (UR[m] - UL[m]);
+    for (int m = 0; m < 4; ++m) Fn[m] = T(0.5) * (fL[m] + fR[m]) - T(0.5) * lam * (UR[m] - UL[m]);
 }
 
 // ---------------------------------------------------------------- traces
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(BLOCK) void k_edge(int nedge, const int* __restrict
             UL[m] = T[offl + (k * 4 + m) * LANES];
             UR[m] = T[offr + (kr * 4 + m) * LANES];
         }
-        llf(gamma, gm1, UL, UR, nx, ny, F);
+        llf<double>(gamma, gm1, UL, UR, nx, ny, F);
         const double w = hl * tab[O::GW + k];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(BLOCK) void k_element(int n, int npad, const double
             for (int j = 0; j < NP; ++j) u = fma(tab[O::PHI + k * NP + j], c[m][j], u);
             U[m] = u;
         }
-        euler_flux(gm1, U, Fx, Fy);
+        euler_flux<double>(gm1, U, Fx, Fy);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const double gr = a00 * Fx[m] + a01 * Fy[m];
@@ -290,17 +292,30 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk_grid)
     return (bid & 7) * chunk + (bid >> 3);
 }
 
-template <int P, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* __restrict__ C, const double* U0,
-                                                 double* out, const double* __restrict__ geo,
+// T = double: everything in FP64.  T = float (mixed precision): the
+// contractions, traces, fluxes and the lift of modes j >= 1 in FP32; the
+// mean mode (j = 0, whose only contribution is the surface flux: grad phi_0 =
+// 0) is accumulated in FP64 from the FP32 fluxes, and 1/det J and the stage
+// update are FP64.  The two sides of an edge see bitwise equal traces and
+// exactly opposite normals, so the FP32 fluxes cancel exactly and the means
+// stay conservative to FP64 rounding.
+// MODE 3 updates the stage-0 state in place: U0 is then unused and the
+// stage-0 values are read through `out` itself, so every pointer can be
+// __restrict__ and the epilogue can stream (different (m, j) are provably
+// different addresses of one base).
+template <int P, int MODE, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* __restrict__ C,
+                                                 const double* __restrict__ U0, double* __restrict__ out,
+                                                 const double* __restrict__ geo,
                                                  const int* __restrict__ snb, const int* __restrict__ sside,
-                                                 const double* __restrict__ sgeo, const double* __restrict__ tab,
-                                                 double gamma, double dt, const double* __restrict__ dt_dev)
+                                                 const double* __restrict__ sgeo, const T* __restrict__ tab,
+                                                 const double* __restrict__ tab64, double gamma, double dt,
+                                                 const double* __restrict__ dt_dev)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
     constexpr int SS = (NE * NP) | 1;
-    __shared__ double phs[3 * SS];
+    __shared__ T phs[3 * SS];
     for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) phs[(i / (NE * NP)) * SS + i % (NE * NP)] = tab[O::PHS + i];
     __syncthreads();
 
@@ -312,21 +327,26 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
         for (int x = 0; x < 4 * NP; ++x) out[so + x * LANES] = 0.0;
         return;
     }
-    const double gm1 = gamma - 1.0;
+    const T gam = T(gamma), gm1 = T(gamma - 1.0);
     const double* g = geo + state_off(e, 6);
-    const double a00 = g[0], a01 = g[LANES], a10 = g[2 * LANES], a11 = g[3 * LANES], idet = g[4 * LANES];
+    const T a00 = T(g[0]), a01 = T(g[LANES]), a10 = T(g[2 * LANES]), a11 = T(g[3 * LANES]);
+    const double idet = g[4 * LANES];
 
-    double c[4][NP];
+    // FP32 compute keeps only the rounded state live; the stage update
+    // re-reads the FP64 state at the end
+    constexpr bool F64 = sizeof(T) == sizeof(double);
+    T c[4][NP];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int j = 0; j < NP; ++j) c[m][j] = C[so + (m * NP + j) * LANES];
+        for (int j = 0; j < NP; ++j) c[m][j] = T(C[so + (m * NP + j) * LANES]);
 
-    double acc[4][NP];
+    double acc0[4] = {0.0, 0.0, 0.0, 0.0};  // mean mode, FP64
+    T acc[4][NP];                          // acc[m][0] unused
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int j = 0; j < NP; ++j) acc[m][j] = 0.0;
+        for (int j = 0; j < NP; ++j) acc[m][j] = T(0);
 
     // surface integral, eq. (surface): the element's own three sides
     const int sides = sside[state_off(e, 1)];
@@ -335,104 +355,97 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
         const int nb = snb[state_off(e, 3) + q * LANES];
         const int qn = (sides >> (2 * q)) & 3;
         const int go = state_off(e, 9) + 3 * q * LANES;
-        const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
+        const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
+        const double hl = sgeo[go + 2 * LANES];
         // neighbour trace at its side qn, at the reversed edge points
-        double UR[NE][4];
+        T UR[NE][4];
 #pragma unroll
         for (int k = 0; k < NE; ++k)
 #pragma unroll
-            for (int m = 0; m < 4; ++m) UR[k][m] = 0.0;
+            for (int m = 0; m < 4; ++m) UR[k][m] = T(0);
         const int nbo = state_off(nb, 4 * NP);
-        const double* tq = phs + qn * SS;
+        const T* tq = phs + qn * SS;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            double cv[4];
+            T cv[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) cv[m] = C[nbo + (m * NP + j) * LANES];
+            for (int m = 0; m < 4; ++m) cv[m] = T(C[nbo + (m * NP + j) * LANES]);
 #pragma unroll
             for (int k = 0; k < NE; ++k) {
-                const double t = tq[(NE - 1 - k) * NP + j];
+                const T t = tq[(NE - 1 - k) * NP + j];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) UR[k][m] = fma(t, cv[m], UR[k][m]);
             }
         }
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
-            const double* tl = tab + O::PHS + (q * NE + k) * NP;
-            double UL[4], F[4];
+            const T* tl = tab + O::PHS + (q * NE + k) * NP;
+            T UL[4], F[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                double u = 0.0;
+                T u = T(0);
 #pragma unroll
                 for (int j = 0; j < NP; ++j) u = fma(tl[j], c[m][j], u);
                 UL[m] = u;
             }
-            llf(gamma, gm1, UL, UR[k], nx, ny, F);
-            const double w = -hl * tab[O::GW + k];
+            llf<T>(gam, gm1, UL, UR[k], nx, ny, F);
+            const double w = -hl * tab64[O::GW + k];
+            const double w0 = w * tab64[O::PHS + (q * NE + k) * NP];  // phi_0 is constant
 #pragma unroll
-            for (int m = 0; m < 4; ++m) F[m] *= w;
+            for (int m = 0; m < 4; ++m) {
+                acc0[m] = fma(w0, double(F[m]), acc0[m]);
+                F[m] *= T(w);
+            }
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int j = 0; j < NP; ++j) acc[m][j] = fma(tl[j], F[m], acc[m][j]);
+                for (int j = 1; j < NP; ++j) acc[m][j] = fma(tl[j], F[m], acc[m][j]);
         }
     }
 
-    // volume integral, eq. (volume)
+    // volume integral, eq. (volume); grad phi_0 = 0, so modes j >= 1 only
 #pragma unroll 1
     for (int k = 0; k < NQ; ++k) {
-        double U[4], Fx[4], Fy[4];
+        T U[4], Fx[4], Fy[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            double u = 0.0;
+            T u = T(0);
 #pragma unroll
             for (int j = 0; j < NP; ++j) u = fma(tab[O::PHI + k * NP + j], c[m][j], u);
             U[m] = u;
         }
-        euler_flux(gm1, U, Fx, Fy);
+        euler_flux<T>(gm1, U, Fx, Fy);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const double gr = a00 * Fx[m] + a01 * Fy[m];
-            const double gs = a10 * Fx[m] + a11 * Fy[m];
+            const T gr = a00 * Fx[m] + a01 * Fy[m];
+            const T gs = a10 * Fx[m] + a11 * Fy[m];
 #pragma unroll
-            for (int j = 0; j < NP; ++j)
+            for (int j = 1; j < NP; ++j)
                 acc[m][j] = fma(tab[O::DRW + k * NP + j], gr, fma(tab[O::DSW + k * NP + j], gs, acc[m][j]));
         }
     }
 
-    // inverse mass matrix 1/det J, then the plain RHS or the SSP-RK3 stage
-    if constexpr (MODE == 0) {
+    // inverse mass matrix 1/det J (FP64), then the RHS or the SSP-RK3 stage
+    const double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int j = 0; j < NP; ++j) out[so + (m * NP + j) * LANES] = idet * acc[m][j];
-    } else {
-        const double h = dt_dev ? dt_dev[0] : dt;
-        double u0[4][NP];
-        if constexpr (MODE != 1) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int j = 0; j < NP; ++j) u0[m][j] = U0[so + (m * NP + j) * LANES];
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                const double L = idet * acc[m][j];
+        for (int j = 0; j < NP; ++j) {
+            const int x = so + (m * NP + j) * LANES;
+            const double L = idet * (j == 0 ? acc0[m] : double(acc[m][j]));
+            if constexpr (MODE == 0) {
+                out[x] = L;
+            } else {
+                const double cs = F64 ? double(c[m][j]) : C[x];
                 if constexpr (MODE == 1) {
-                    c[m][j] = c[m][j] + h * L;
+                    out[x] = cs + h * L;
                 } else if constexpr (MODE == 2) {
-                    c[m][j] = 0.75 * u0[m][j] + 0.25 * (c[m][j] + h * L);
+                    out[x] = 0.75 * U0[x] + 0.25 * (cs + h * L);
                 } else {
-                    c[m][j] = (1.0 / 3.0) * u0[m][j] + (2.0 / 3.0) * (c[m][j] + h * L);
+                    out[x] = (1.0 / 3.0) * out[x] + (2.0 / 3.0) * (cs + h * L);
                 }
             }
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int j = 0; j < NP; ++j) out[so + (m * NP + j) * LANES] = c[m][j];
-    }
+        }
 }
 
 // ---------------------------------------------------------------- CFL step
@@ -545,19 +558,28 @@ struct Launch {
         }
 #undef DG_ELEM
     }
-    static void stage(const MeshDev& m, int mode, const double* C, const double* U0, double* out, double dt,
-                      const double* dt_dev, hipStream_t s)
+    static void stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out,
+                      double dt, const double* dt_dev, hipStream_t s)
     {
         const int nb = (m.npad + BLOCK - 1) / BLOCK;
         dim3 g((nb + 7) / 8 * 8);
-#define DG_STAGE(MODE)                                                                                         \
-    k_stage<P, MODE><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, m.tab, \
-                                         m.gamma, dt, dt_dev)
-        switch (mode) {
-        case 0: DG_STAGE(0); break;
-        case 1: DG_STAGE(1); break;
-        case 2: DG_STAGE(2); break;
-        default: DG_STAGE(3); break;
+#define DG_STAGE(MODE, T, TAB)                                                                                  \
+    k_stage<P, MODE, T><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, TAB, \
+                                            m.tab, m.gamma, dt, dt_dev)
+        if (mixed) {
+            switch (mode) {
+            case 0: DG_STAGE(0, float, m.tab32); break;
+            case 1: DG_STAGE(1, float, m.tab32); break;
+            case 2: DG_STAGE(2, float, m.tab32); break;
+            default: DG_STAGE(3, float, m.tab32); break;
+            }
+        } else {
+            switch (mode) {
+            case 0: DG_STAGE(0, double, m.tab); break;
+            case 1: DG_STAGE(1, double, m.tab); break;
+            case 2: DG_STAGE(2, double, m.tab); break;
+            default: DG_STAGE(3, double, m.tab); break;
+            }
         }
 #undef DG_STAGE
     }

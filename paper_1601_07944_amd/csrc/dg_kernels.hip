@@ -68,10 +68,10 @@ void launch_element(const MeshDev& m, int mode, const double* C, const double* U
     DG_DISPATCH_P(m.p, element(m, mode, C, U0, out, S, dt, dt_dev, Tn, s));
 }
 
-void launch_stage(const MeshDev& m, int mode, const double* C, const double* U0, double* out, double dt,
+void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out, double dt,
                   const double* dt_dev, hipStream_t s)
 {
-    DG_DISPATCH_P(m.p, stage(m, mode, C, U0, out, dt, dt_dev, s));
+    DG_DISPATCH_P(m.p, stage(m, mode, mixed, C, U0, out, dt, dt_dev, s));
 }
 
 int dt_partials(const MeshDev& m) { return (m.n + BLOCK - 1) / BLOCK; }
