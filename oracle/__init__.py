@@ -30,7 +30,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 def build(force: bool = False) -> str:
     """Compile dg_oracle.c with gcc (-O2, no fast-math, OpenMP loop pragmas)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    srcs = [_SRC, os.path.join(_HERE, "dg_oracle_forward.inc")]
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in srcs):
         tmp = _LIB + f".tmp{os.getpid()}"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
@@ -66,6 +67,10 @@ def _configure(lib):
     lib.orc_max_dt.restype = ctypes.c_int
     lib.orc_rk3_step.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
     lib.orc_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+    _cp = ctypes.POINTER(ctypes.c_double * 2)
+    lib.orc_cs_rhs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.orc_rhs_vjp.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    lib.orc_rk3_step_vjp.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp, _dp]
     lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_set_threads.restype = ctypes.c_int
     return lib
@@ -80,8 +85,13 @@ def _load():
 
 
 def source() -> str:
+    """The oracle's C source as one file (the forward include inlined), for
+    compiling modified copies in the mutation tests."""
     with open(_SRC) as f:
-        return f.read()
+        src = f.read()
+    with open(os.path.join(_HERE, "dg_oracle_forward.inc")) as f:
+        inc = f.read()
+    return src.replace('#include "dg_oracle_forward.inc"', inc)
 
 
 def load_variant(src: str, path: str):
@@ -172,6 +182,31 @@ class Oracle:
         R = np.empty_like(C)
         self._lib.orc_rhs(self._ctx, _p(C), _p(R))
         return R
+
+    def rhs_complex(self, C):
+        """The forward operator on a complex state (complex-step derivatives:
+        Im R(C + i h d) / h = (dR/dC) d to rounding for tiny h)."""
+        C = np.ascontiguousarray(C, dtype=np.complex128)
+        assert C.shape == (self.n, 4, self.np)
+        R = np.empty_like(C)
+        self._lib.orc_cs_rhs(self._ctx, C.ctypes.data, R.ctypes.data)
+        return R
+
+    def rhs_vjp(self, C, Rbar):
+        """Hand-written adjoint: (dR/dC)^T Rbar."""
+        C = self._state(C)
+        Rbar = self._state(Rbar)
+        Cb = np.empty_like(C)
+        self._lib.orc_rhs_vjp(self._ctx, _p(C), _p(Rbar), _p(Cb))
+        return Cb
+
+    def rk3_step_vjp(self, C, dt, ubar):
+        """Adjoint of one SSP-RK3 step with fixed dt."""
+        C = self._state(C)
+        ubar = self._state(ubar)
+        Cb = np.empty_like(C)
+        self._lib.orc_rk3_step_vjp(self._ctx, _p(C), float(dt), _p(ubar), _p(Cb))
+        return Cb
 
     def quad_points(self):
         xy = np.empty((self.n, self.nq, 2))

@@ -43,6 +43,7 @@
  *     r_i = det J_i / perimeter_i and the state at the cell average
  *     sqrt(2) c_{i,0}.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -272,104 +273,32 @@ void orc_eval(const orc_ctx *c, const double *C, int npts, const double *r, cons
     free(phi);
 }
 
-/* ------------------------------------------------------------ physics */
-/* Euler flux, eq. (euler), with p = (gamma-1)(E - rho |v|^2 / 2) */
-static void euler_flux(double gamma, const double U[M], double Fx[M], double Fy[M])
-{
-    double rho = U[0], u = U[1] / rho, v = U[2] / rho, E = U[3];
-    double pr = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
-    Fx[0] = rho * u;
-    Fx[1] = rho * u * u + pr;
-    Fx[2] = rho * u * v;
-    Fx[3] = u * (E + pr);
-    Fy[0] = rho * v;
-    Fy[1] = rho * u * v;
-    Fy[2] = rho * v * v + pr;
-    Fy[3] = v * (E + pr);
-}
+/* ------------------------------------------------------- forward operator */
+/* double precision: orc_euler_flux, orc_llf, orc_rhs_element, orc_rhs */
+#define R_T double
+#define R_ABS(x) fabs(x)
+#define R_SQRT(x) sqrt(x)
+#define R_GE(a, b) ((a) >= (b))
+#define R_NAME(name) orc_##name
+#include "dg_oracle_forward.inc"
+#undef R_T
+#undef R_ABS
+#undef R_SQRT
+#undef R_GE
+#undef R_NAME
 
-static void llf(double gamma, const double UL[M], const double UR[M], double nx, double ny, double Fn[M])
-{
-    double FxL[M], FyL[M], FxR[M], FyR[M];
-    euler_flux(gamma, UL, FxL, FyL);
-    euler_flux(gamma, UR, FxR, FyR);
-    double vnL = (UL[1] / UL[0]) * nx + (UL[2] / UL[0]) * ny;
-    double vnR = (UR[1] / UR[0]) * nx + (UR[2] / UR[0]) * ny;
-    double pL = (gamma - 1.0) * (UL[3] - 0.5 * UL[0] * ((UL[1] / UL[0]) * (UL[1] / UL[0]) + (UL[2] / UL[0]) * (UL[2] / UL[0])));
-    double pR = (gamma - 1.0) * (UR[3] - 0.5 * UR[0] * ((UR[1] / UR[0]) * (UR[1] / UR[0]) + (UR[2] / UR[0]) * (UR[2] / UR[0])));
-    double lamL = fabs(vnL) + sqrt(gamma * pL / UL[0]);
-    double lamR = fabs(vnR) + sqrt(gamma * pR / UR[0]);
-    double lam = lamL >= lamR ? lamL : lamR;
-    for (int m = 0; m < M; ++m) {
-        double fL = FxL[m] * nx + FyL[m] * ny;
-        double fR = FxR[m] * nx + FyR[m] * ny;
-        Fn[m] = 0.5 * (fL + fR) - 0.5 * lam * (UR[m] - UL[m]);
-    }
-}
-
-/* ------------------------------------------------------------------ RHS */
-static void rhs_element(const orc_ctx *c, const double *C, double *R, int64_t i)
-{
-    const int np = c->np, nq = c->nq, ne = c->ne;
-    double adj[2][2], det;
-    element_geometry(c, i, adj, &det);
-    const double *ci = C + i * M * np;
-    double vol[M][NP_MAX], sur[M][NP_MAX];
-    memset(vol, 0, sizeof(vol));
-    memset(sur, 0, sizeof(sur));
-
-    /* volume integral, eq. (volume) */
-    for (int k = 0; k < nq; ++k) {
-        double U[M], Fx[M], Fy[M];
-        for (int m = 0; m < M; ++m) {
-            U[m] = 0.0;
-            for (int j = 0; j < np; ++j) U[m] += ci[m * np + j] * c->phi_v[k * np + j];
-        }
-        euler_flux(c->gamma, U, Fx, Fy);
-        for (int m = 0; m < M; ++m) {
-            double Gr = adj[0][0] * Fx[m] + adj[0][1] * Fy[m];
-            double Gs = adj[1][0] * Fx[m] + adj[1][1] * Fy[m];
-            for (int j = 0; j < np; ++j)
-                vol[m][j] += c->qw[k] * (c->dr_v[k * np + j] * Gr + c->ds_v[k * np + j] * Gs);
-        }
-    }
-
-    /* surface integral, eq. (surface): the three sides of this element */
-    for (int q = 0; q < 3; ++q) {
-        int64_t nb = c->nbr[i * 3 + q];
-        int qn = c->nbs[i * 3 + q];
-        const double *cn = C + nb * M * np;
-        double nx, ny, l;
-        side_geometry(c, i, q, &nx, &ny, &l);
-        for (int k = 0; k < ne; ++k) {
-            const double *phiL = c->phi_s + (q * ne + k) * np;
-            const double *phiR = c->phi_s + (qn * ne + (ne - 1 - k)) * np;
-            double UL[M], UR[M], Fn[M];
-            for (int m = 0; m < M; ++m) {
-                UL[m] = 0.0;
-                UR[m] = 0.0;
-                for (int j = 0; j < np; ++j) {
-                    UL[m] += ci[m * np + j] * phiL[j];
-                    UR[m] += cn[m * np + j] * phiR[j];
-                }
-            }
-            llf(c->gamma, UL, UR, nx, ny, Fn);
-            for (int m = 0; m < M; ++m)
-                for (int j = 0; j < np; ++j) sur[m][j] += l * c->gw[k] * phiL[j] * Fn[m];
-        }
-    }
-
-    /* eq. (2ddg0): orthonormal basis, so the inverse mass matrix is 1/det J */
-    for (int m = 0; m < M; ++m)
-        for (int j = 0; j < np; ++j) R[(i * M + m) * np + j] = (vol[m][j] - sur[m][j]) / det;
-}
-
-/* R = L(C), user layout [n][M][np] */
-void orc_rhs(const orc_ctx *c, const double *C, double *R)
-{
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < c->n; ++i) rhs_element(c, C, R, i);
-}
+/* double complex (complex-step derivatives): orc_cs_rhs */
+#define R_T double _Complex
+#define R_ABS(x) (creal(x) < 0.0 ? -(x) : (x))
+#define R_SQRT(x) csqrt(x)
+#define R_GE(a, b) (creal(a) >= creal(b))
+#define R_NAME(name) orc_cs_##name
+#include "dg_oracle_forward.inc"
+#undef R_T
+#undef R_ABS
+#undef R_SQRT
+#undef R_GE
+#undef R_NAME
 
 /* L2 projection of point values u[n][nq][M] at the volume points:
  * c_j = sum_k w_k phi_j(r_k) u(x(r_k))  (mass matrix det J * I) */
@@ -450,4 +379,197 @@ int orc_set_threads(int n)
     (void)n;
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------- adjoint */
+/* Hand-written discrete adjoint (vector-Jacobian product) of orc_rhs:
+ * Cbar = (dR/dC)^T Rbar.  Reverse mode through each element's arithmetic in
+ * the order of rhs_element: the surface flux of side q contributes to this
+ * element (left state) and to its neighbour (right state), the volume term
+ * to this element only.  The scatter into the neighbour makes the loop
+ * serial.  Ties of the wave-speed max take the left branch; d|x|/dx at 0 is
+ * +1. */
+
+/* reverse of euler_flux: (Fx_bar, Fy_bar) -> U_bar (accumulated) */
+static void euler_flux_vjp(double gamma, const double U[M], const double Fxb[M], const double Fyb[M], double Ub[M])
+{
+    const double g1 = gamma - 1.0;
+    double rho = U[0], u = U[1] / rho, v = U[2] / rho, E = U[3];
+    double pr = g1 * (E - 0.5 * rho * (u * u + v * v));
+    /* Fx = (rho u, rho u u + p, rho u v, u (E + p)), Fy = (rho v, rho u v, rho v v + p, v (E + p)) */
+    double rhob = Fxb[0] * u + Fxb[1] * u * u + Fxb[2] * u * v + Fyb[0] * v + Fyb[1] * u * v + Fyb[2] * v * v;
+    double ub = Fxb[0] * rho + Fxb[1] * 2.0 * rho * u + Fxb[2] * rho * v + Fxb[3] * (E + pr) + Fyb[1] * rho * v;
+    double vb = Fxb[2] * rho * u + Fyb[0] * rho + Fyb[1] * rho * u + Fyb[2] * 2.0 * rho * v + Fyb[3] * (E + pr);
+    double pb = Fxb[1] + Fxb[3] * u + Fyb[2] + Fyb[3] * v;
+    double Eb = Fxb[3] * u + Fyb[3] * v;
+    /* p = g1 (E - rho (u^2 + v^2) / 2) */
+    Eb += g1 * pb;
+    rhob += -0.5 * g1 * (u * u + v * v) * pb;
+    ub += -g1 * rho * u * pb;
+    vb += -g1 * rho * v * pb;
+    /* u = U1 / rho, v = U2 / rho */
+    Ub[1] += ub / rho;
+    Ub[2] += vb / rho;
+    rhob += -(ub * u + vb * v) / rho;
+    Ub[0] += rhob;
+    Ub[3] += Eb;
+}
+
+/* reverse of llf: Fn_bar -> (UL_bar, UR_bar) (accumulated) */
+static void llf_vjp(double gamma, const double UL[M], const double UR[M], double nx, double ny, const double Fb[M],
+                    double ULb[M], double URb[M])
+{
+    const double g1 = gamma - 1.0;
+    const double *Us[2] = {UL, UR};
+    double *Ubs[2] = {ULb, URb};
+    double lam_s[2], vn_s[2], c_s[2], u_s[2], v_s[2], p_s[2];
+    for (int side = 0; side < 2; ++side) {
+        const double *U = Us[side];
+        double u = U[1] / U[0], v = U[2] / U[0];
+        double p = g1 * (U[3] - 0.5 * U[0] * (u * u + v * v));
+        u_s[side] = u;
+        v_s[side] = v;
+        p_s[side] = p;
+        vn_s[side] = u * nx + v * ny;
+        c_s[side] = sqrt(gamma * p / U[0]);
+        lam_s[side] = fabs(vn_s[side]) + c_s[side];
+    }
+    int left_max = lam_s[0] >= lam_s[1];
+    double lam = left_max ? lam_s[0] : lam_s[1];
+    double lamb = 0.0;
+    for (int m = 0; m < M; ++m) {
+        /* Fn = 0.5 (fL + fR) - 0.5 lam (UR - UL) */
+        lamb += -0.5 * Fb[m] * (UR[m] - UL[m]);
+        URb[m] += -0.5 * lam * Fb[m];
+        ULb[m] += 0.5 * lam * Fb[m];
+    }
+    for (int side = 0; side < 2; ++side) {
+        const double *U = Us[side];
+        double *Ub = Ubs[side];
+        /* f = Fx nx + Fy ny with weight 0.5 from the average */
+        double Fxb[M], Fyb[M];
+        for (int m = 0; m < M; ++m) {
+            Fxb[m] = 0.5 * Fb[m] * nx;
+            Fyb[m] = 0.5 * Fb[m] * ny;
+        }
+        euler_flux_vjp(gamma, U, Fxb, Fyb, Ub);
+        /* lam_side = |vn| + c, c = sqrt(gamma p / rho) */
+        double lsb = (side == 0) == (left_max != 0) ? lamb : 0.0;
+        if (lsb == 0.0) continue;
+        double vnb = lsb * (vn_s[side] >= 0.0 ? 1.0 : -1.0);
+        double cb = lsb;
+        double rho = U[0], u = u_s[side], v = v_s[side], p = p_s[side], c = c_s[side];
+        double pb = cb * gamma / (2.0 * c * rho);
+        double rhob = -cb * gamma * p / (2.0 * c * rho * rho);
+        double ub = vnb * nx, vb = vnb * ny;
+        /* p = g1 (E - rho (u^2 + v^2) / 2) */
+        Ub[3] += g1 * pb;
+        rhob += -0.5 * g1 * (u * u + v * v) * pb;
+        ub += -g1 * rho * u * pb;
+        vb += -g1 * rho * v * pb;
+        Ub[1] += ub / rho;
+        Ub[2] += vb / rho;
+        rhob += -(ub * u + vb * v) / rho;
+        Ub[0] += rhob;
+    }
+}
+
+void orc_rhs_vjp(const orc_ctx *c, const double *C, const double *Rb, double *Cb)
+{
+    const int np = c->np, nq = c->nq, ne = c->ne;
+    memset(Cb, 0, sizeof(double) * (size_t)c->n * M * np);
+    for (int64_t i = 0; i < c->n; ++i) {
+        double adj[2][2], det;
+        element_geometry(c, i, adj, &det);
+        const double *ci = C + i * M * np;
+        double *cbi = Cb + i * M * np;
+        double Rs[M][NP_MAX]; /* Rbar / det J: cotangent of (volume - surface) */
+        for (int m = 0; m < M; ++m)
+            for (int j = 0; j < np; ++j) Rs[m][j] = Rb[(i * M + m) * np + j] / det;
+
+        /* volume: vol[m][j] += w_k (dr_jk Gr_m + ds_jk Gs_m) */
+        for (int k = 0; k < nq; ++k) {
+            double U[M], Fxb[M], Fyb[M], Ub[M] = {0.0, 0.0, 0.0, 0.0};
+            for (int m = 0; m < M; ++m) {
+                U[m] = 0.0;
+                for (int j = 0; j < np; ++j) U[m] += ci[m * np + j] * c->phi_v[k * np + j];
+            }
+            for (int m = 0; m < M; ++m) {
+                double Grb = 0.0, Gsb = 0.0;
+                for (int j = 0; j < np; ++j) {
+                    Grb += c->qw[k] * c->dr_v[k * np + j] * Rs[m][j];
+                    Gsb += c->qw[k] * c->ds_v[k * np + j] * Rs[m][j];
+                }
+                /* Gr = a00 Fx + a01 Fy, Gs = a10 Fx + a11 Fy */
+                Fxb[m] = adj[0][0] * Grb + adj[1][0] * Gsb;
+                Fyb[m] = adj[0][1] * Grb + adj[1][1] * Gsb;
+            }
+            euler_flux_vjp(c->gamma, U, Fxb, Fyb, Ub);
+            for (int m = 0; m < M; ++m)
+                for (int j = 0; j < np; ++j) cbi[m * np + j] += c->phi_v[k * np + j] * Ub[m];
+        }
+
+        /* surface: sur[m][j] += l w_k phi_j(r_qk) Fn_m; R has -sur */
+        for (int q = 0; q < 3; ++q) {
+            int64_t nb = c->nbr[i * 3 + q];
+            int qn = c->nbs[i * 3 + q];
+            const double *cn = C + nb * M * np;
+            double *cbn = Cb + nb * M * np;
+            double nx, ny, l;
+            side_geometry(c, i, q, &nx, &ny, &l);
+            for (int k = 0; k < ne; ++k) {
+                const double *phiL = c->phi_s + (q * ne + k) * np;
+                const double *phiR = c->phi_s + (qn * ne + (ne - 1 - k)) * np;
+                double UL[M], UR[M], Fb[M], ULb[M] = {0.0, 0.0, 0.0, 0.0}, URb[M] = {0.0, 0.0, 0.0, 0.0};
+                for (int m = 0; m < M; ++m) {
+                    UL[m] = 0.0;
+                    UR[m] = 0.0;
+                    for (int j = 0; j < np; ++j) {
+                        UL[m] += ci[m * np + j] * phiL[j];
+                        UR[m] += cn[m * np + j] * phiR[j];
+                    }
+                    Fb[m] = 0.0;
+                    for (int j = 0; j < np; ++j) Fb[m] += -l * c->gw[k] * phiL[j] * Rs[m][j];
+                }
+                llf_vjp(c->gamma, UL, UR, nx, ny, Fb, ULb, URb);
+                for (int m = 0; m < M; ++m)
+                    for (int j = 0; j < np; ++j) {
+                        cbi[m * np + j] += phiL[j] * ULb[m];
+                        cbn[m * np + j] += phiR[j] * URb[m];
+                    }
+            }
+        }
+    }
+}
+
+/* Adjoint of one SSP-RK3 step with a fixed dt (dt is not differentiated):
+ * given ubar of the result, Cb = d(step)/dC ^T ubar.  Recomputes the stages:
+ *   u2bar = 2/3 ubar + 2/3 dt J(u2)^T ubar
+ *   u1bar = 1/4 u2bar + 1/4 dt J(u1)^T u2bar
+ *   Cb    = 1/3 ubar + 3/4 u2bar + u1bar + dt J(u)^T u1bar */
+void orc_rk3_step_vjp(const orc_ctx *c, const double *C, double dt, const double *ub, double *Cb)
+{
+    size_t len = (size_t)c->n * M * c->np;
+    double *L = (double *)malloc(sizeof(double) * len);
+    double *u1 = (double *)malloc(sizeof(double) * len);
+    double *u2 = (double *)malloc(sizeof(double) * len);
+    double *t = (double *)malloc(sizeof(double) * len);
+    double *u2b = (double *)malloc(sizeof(double) * len);
+    double *u1b = (double *)malloc(sizeof(double) * len);
+    orc_rhs(c, C, L);
+    for (size_t x = 0; x < len; ++x) u1[x] = C[x] + dt * L[x];
+    orc_rhs(c, u1, L);
+    for (size_t x = 0; x < len; ++x) u2[x] = 0.75 * C[x] + 0.25 * (u1[x] + dt * L[x]);
+    orc_rhs_vjp(c, u2, ub, t);
+    for (size_t x = 0; x < len; ++x) u2b[x] = (2.0 / 3.0) * ub[x] + (2.0 / 3.0) * dt * t[x];
+    orc_rhs_vjp(c, u1, u2b, t);
+    for (size_t x = 0; x < len; ++x) u1b[x] = 0.25 * u2b[x] + 0.25 * dt * t[x];
+    orc_rhs_vjp(c, C, u1b, t);
+    for (size_t x = 0; x < len; ++x) Cb[x] = (1.0 / 3.0) * ub[x] + 0.75 * u2b[x] + u1b[x] + dt * t[x];
+    free(L);
+    free(u1);
+    free(u2);
+    free(t);
+    free(u2b);
+    free(u1b);
 }

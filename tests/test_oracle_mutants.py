@@ -28,11 +28,11 @@ MUTANTS = {
     "side1_direction": ("*r = 0.5 * (1.0 - x);\n        *s = 0.5 * (1.0 + x);", "*r = 0.5 * (1.0 + x);\n        *s = 0.5 * (1.0 - x);"),
     "dissipation_sign": ("- 0.5 * lam * (UR[m] - UL[m])", "+ 0.5 * lam * (UR[m] - UL[m])"),
     "pressure_no_half": (
-        "double pr = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));",
-        "double pr = (gamma - 1.0) * (E - rho * (u * u + v * v));",
+        "R_T pr = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));",
+        "R_T pr = (gamma - 1.0) * (E - rho * (u * u + v * v));",
     ),
-    "sound_speed_no_gamma": ("sqrt(gamma * pL / UL[0])", "sqrt(pL / UL[0])"),
-    "wave_speed_min": ("lamL >= lamR ? lamL : lamR", "lamL >= lamR ? lamR : lamL"),
+    "sound_speed_no_gamma": ("R_SQRT(gamma * pL / UL[0])", "R_SQRT(pL / UL[0])"),
+    "wave_speed_min": ("R_GE(lamL, lamR) ? lamL : lamR", "R_GE(lamL, lamR) ? lamR : lamL"),
     "rk3_stage2_weights": ("0.75 * C[x] + 0.25 * (u1[x]", "0.5 * C[x] + 0.5 * (u1[x]"),
     "inverse_mass_area": ("(vol[m][j] - sur[m][j]) / det", "(vol[m][j] - sur[m][j]) / (0.5 * det)"),
     "basis_normalisation": ("double K = sqrt(2.0 * (2 * a + 1) * (a + b + 1));", "double K = sqrt((2.0 * a + 1) * (a + b + 1));"),
@@ -45,6 +45,12 @@ MUTANTS = {
     "dt_half_perimeter": ("per += 2.0 * l;", "per += l;"),
     "neighbour_uses_own_coeffs": ("UR[m] += cn[m * np + j] * phiR[j];", "UR[m] += ci[m * np + j] * phiR[j];"),
     "jacobi_derivative_factor": ("return 0.5 * (double)(n + a + b + 1) * jacobi", "return (double)(n + a + b + 1) * jacobi"),
+    # adjoint
+    "vjp_no_neighbour_cotangent": ("cbn[m * np + j] += phiR[j] * URb[m];", "cbn[m * np + j] += 0.0 * URb[m];"),
+    "vjp_wave_speed_branch": ("int left_max = lam_s[0] >= lam_s[1];", "int left_max = lam_s[0] < lam_s[1];"),
+    "vjp_pressure_velocity_term": ("ub += -g1 * rho * u * pb;\n    vb += -g1 * rho * v * pb;\n    /* u = U1", "ub += 0.0 * pb;\n    vb += -g1 * rho * v * pb;\n    /* u = U1"),
+    "vjp_metric_not_transposed": ("Fxb[m] = adj[0][0] * Grb + adj[1][0] * Gsb;", "Fxb[m] = adj[0][0] * Grb + adj[0][1] * Gsb;"),
+    "vjp_rk_stage_weight": ("u1b[x] = 0.25 * u2b[x] + 0.25 * dt * t[x];", "u1b[x] = 0.25 * u2b[x] + 0.75 * dt * t[x];"),
 }
 
 
@@ -143,7 +149,25 @@ def pin_rk3(lib):
     return math.log2(e[0] / e[1]) > 2.8
 
 
-PINS = [pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
+def pin_adjoint(lib):
+    mesh = W.delaunay_mesh(40, 3)
+    ok = True
+    for p in (1, 3):
+        orc = O.Oracle(mesh, p, lib=lib)
+        rng = np.random.default_rng(p)
+        C = W.random_state(mesh.n_elem, orc.np, seed=p)
+        d = rng.normal(size=C.shape)
+        Rb = rng.normal(size=C.shape)
+        Jd = orc.rhs_complex(C + 1e-30j * d).imag / 1e-30
+        lhs = np.sum(Rb * Jd)
+        ok &= abs(lhs - np.sum(orc.rhs_vjp(C, Rb) * d)) <= 1e-13 * np.abs(Rb * Jd).sum()
+        dt, _ = orc.max_dt(C, 0.3 / (2 * p + 1))
+        fd = (orc.rk3_step(C + 1e-6 * d, dt) - orc.rk3_step(C - 1e-6 * d, dt)) / 2e-6
+        ok &= abs(np.sum(Rb * fd) - np.sum(orc.rk3_step_vjp(C, dt, Rb) * d)) <= 1e-8 * np.abs(Rb * fd).sum()
+    return bool(ok)
+
+
+PINS = [pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
 
 
 def run_pins(lib):
