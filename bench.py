@@ -235,6 +235,46 @@ def main():
     torch.cuda.synchronize()
     mixed_err = float(torch.linalg.norm(Cmx - C64) / torch.linalg.norm(C64))
 
+    # adjoint: reverse sweep over the same number of steps with a fixed dt
+    # (checkpoint every 20 steps, segment recomputation keeping the stage
+    # states, then the step adjoints) against the forward steps
+    from paper_1601_07944_amd import adjoint as A
+
+    nadj = max(20, min(args.steps, 200) // 20 * 20)
+    Ca = C.clone()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(nadj):
+        dm.rk_step(Ca, dt_host)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1)
+    ckpts = []
+    Ca = C.clone()
+    for n in range(nadj):
+        if n % 20 == 0:
+            ckpts.append(Ca.clone())
+        dm.rk_step(Ca, dt_host)
+    gN = torch.randn_like(Ca)
+    A.backward_sweep(dm, ckpts[:1], dt_host, 20, 20, gN)  # warm-up
+    torch.cuda.synchronize()
+    e0.record()
+    A.backward_sweep(dm, ckpts, dt_host, nadj, 20, gN)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_rev = e0.elapsed_time(e1)
+    # the step adjoints alone (stage states already stored)
+    Cs, u1s, u2s = C.clone(), dm.empty_state(), dm.empty_state()
+    dm.rk_step_stages(Cs, u1s, u2s, dt_host)
+    g = gN.clone()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(nadj):
+        g = dm.rk_step_vjp(C, g, dt_host, u1=u1s, u2=u2s)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_vjp = e0.elapsed_time(e1)
+
     # the paper's edge-wise organisation (3 kernels per RHS), same steps
     dm.set_surface_mode(dm.SURFACE_EDGEWISE)
     for _ in range(5):
@@ -290,7 +330,14 @@ def main():
             "rel_l2_vs_fp64_after_steps": mixed_err,
             "steps": args.steps,
         },
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": {
+            "ratio": ms_rev / ms_fwd,
+            "ratio_without_recompute": ms_vjp / ms_fwd,
+            "steps": nadj,
+            "checkpoint_every": 20,
+            "ms_forward": ms_fwd,
+            "ms_reverse": ms_rev,
+        },
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, p, args.cpu_seconds)

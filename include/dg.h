@@ -87,7 +87,8 @@ typedef struct {
     int64_t n_edges;    /* edges (1.5 n_elem on a periodic mesh) */
     int64_t state_len;  /* doubles in one internal-layout state */
     int64_t ws_rhs;     /* workspace bytes for dg_rhs and dg_max_dt */
-    int64_t ws_step;    /* workspace bytes for dg_rk_step */
+    int64_t ws_step;    /* workspace bytes for dg_rk_step and dg_rk_step_stages */
+    int64_t ws_vjp;     /* workspace bytes for dg_rk_step_vjp */
 } dg_info;
 
 /* Checks a mesh without touching the GPU (no HIP call).  Arguments as for
@@ -158,6 +159,43 @@ int dg_max_dt(dg_mesh m, const double* C_dev, double cfl, double* dt_dev, double
 int dg_rk_step(dg_mesh m, double* C_dev, double dt, const double* dt_dev, dg_precision prec, void* ws_dev,
                void* stream);
 
+/* Adjoint (vector-Jacobian product) of dg_rhs, the derivative of the
+ * discrete operator of eq. (2ddg0) transposed: Cbar = (dR/dC)^T Rbar, all
+ * FP64, internal layout.  Element-wise gather form: no cotangent is
+ * scattered across elements (no atomics; deterministic).  At exact ties of
+ * the Lax-Friedrichs wave-speed max the left state's branch is taken, and
+ * d|x|/dx = +1 at 0.  Cbar must not overlap C or Rbar.  ws: ws_rhs bytes. */
+int dg_rhs_vjp(dg_mesh m, const double* C_dev, const double* Rbar_dev, double* Cbar_dev, void* ws_dev, void* stream);
+
+/* Adjoint of one dg_rk_step (SSP-RK3) at state C_dev with the step length
+ * held fixed (dt_dev[0] if dt_dev is not NULL, else dt; the step length is
+ * not differentiated):
+ *   u2bar = 2/3 ubar + 2/3 dt J(u2)^T ubar
+ *   u1bar = 1/4 u2bar + 1/4 dt J(u1)^T u2bar
+ *   Cbar  = 1/3 ubar + 3/4 u2bar + u1bar + dt J(C)^T u1bar
+ * with J = dR/dC.  The stage states u1, u2 are recomputed unless the caller
+ * passes them (u1_dev, u2_dev from dg_rk_step_stages, NULL otherwise).
+ * Cbar must not overlap the other arrays.  ws: ws_vjp bytes of dg_info. */
+int dg_rk_step_vjp(dg_mesh m, const double* C_dev, double dt, const double* dt_dev, const double* u1_dev,
+                   const double* u2_dev, const double* ubar_dev, double* Cbar_dev, void* ws_dev, void* stream);
+
+/* dg_rk_step that also keeps its two stage states (for dg_rk_step_vjp):
+ * u1_dev, u2_dev receive u1 and u2 of the step (state_len doubles each,
+ * caller-owned); C_dev is advanced in place.  Element-wise surface mode,
+ * FP64.  ws: ws_step bytes. */
+int dg_rk_step_stages(dg_mesh m, double* C_dev, double dt, const double* dt_dev, double* u1_dev, double* u2_dev,
+                      void* ws_dev, void* stream);
+
+/* U_h at the volume quadrature points, u_dev [N][n_vol_points][4] (user
+ * order): the modes-to-points contraction on its own, for functionals of
+ * the solution. */
+int dg_eval_points(dg_mesh m, const double* C_dev, double* u_dev, void* stream);
+
+/* Physical quadrature weights det J_i * w_k, w_dev [N][n_vol_points] (user
+ * order): sum_k w_ik f(x_ik) integrates f over element i exactly for
+ * polynomials of degree <= 2p. */
+int dg_quad_weights(dg_mesh m, double* w_dev, void* stream);
+
 /* Organisation of the surface integral (Section "Surface Integration
  * Kernel" discusses both):
  *   DG_SURFACE_ELEMENTWISE (default): one fused kernel per right-hand side
@@ -187,7 +225,8 @@ enum {
     DG_KERNEL_ELEMENT = 2,  /* edge-wise path: volume + lift + inverse mass (+ RK stage) */
     DG_KERNEL_DT = 3,       /* CFL reduction (both passes) */
     DG_KERNEL_STAGE = 4,    /* element-wise path: whole RHS (+ RK stage) in one kernel */
-    DG_KERNEL_KINDS = 5
+    DG_KERNEL_VJP = 5,      /* adjoint of the element-wise RHS (+ RK stage adjoint) */
+    DG_KERNEL_KINDS = 6
 };
 int dg_timing_enable(dg_mesh m, int on);
 int dg_timing_read(dg_mesh m, double* ms, int64_t* count, int n);

@@ -43,6 +43,11 @@ EXPORTS = [
     "dg_rhs",
     "dg_max_dt",
     "dg_rk_step",
+    "dg_rhs_vjp",
+    "dg_rk_step_vjp",
+    "dg_rk_step_stages",
+    "dg_eval_points",
+    "dg_quad_weights",
     "dg_set_surface_mode",
     "dg_timing_enable",
     "dg_timing_read",
@@ -69,6 +74,7 @@ class dg_info(ctypes.Structure):
         ("state_len", ctypes.c_int64),
         ("ws_rhs", ctypes.c_int64),
         ("ws_step", ctypes.c_int64),
+        ("ws_vjp", ctypes.c_int64),
     ]
 
 
@@ -98,6 +104,11 @@ def load(path: str = LIB_PATH):
     lib.dg_rhs.argtypes = [_vp, _vp, _vp, i32, _vp, _vp]
     lib.dg_max_dt.argtypes = [_vp, _vp, ctypes.c_double, _vp, _dp, _vp, _vp]
     lib.dg_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _vp, i32, _vp, _vp]
+    lib.dg_rhs_vjp.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    lib.dg_rk_step_vjp.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.dg_rk_step_stages.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
+    lib.dg_eval_points.argtypes = [_vp, _vp, _vp, _vp]
+    lib.dg_quad_weights.argtypes = [_vp, _vp, _vp]
     lib.dg_set_surface_mode.argtypes = [_vp, i32]
     lib.dg_timing_enable.argtypes = [_vp, i32]
     lib.dg_timing_read.argtypes = [_vp, _dp, ctypes.POINTER(i64), i32]
@@ -266,7 +277,7 @@ class DGMesh:
                                    ctypes.byref(host) if to_host else None, _ptr(ws), _stream(stream)))
         return dt_dev, (host.value if to_host else None)
 
-    KERNELS = ("traces", "edge", "element", "dt", "stage")
+    KERNELS = ("traces", "edge", "element", "dt", "stage", "vjp")
     SURFACE_ELEMENTWISE = 0
     SURFACE_EDGEWISE = 1
 
@@ -283,6 +294,44 @@ class DGMesh:
         cnt = (ctypes.c_int64 * nk)()
         _check(self._lib.dg_timing_read(self._h, ms, cnt, nk))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
+
+    def rhs_vjp(self, C, Rbar, out=None, stream=None):
+        out = self.empty_state() if out is None else out
+        _check(self._lib.dg_rhs_vjp(self._h, _ptr(C), _ptr(Rbar), _ptr(out), None, _stream(stream)))
+        return out
+
+    def rk_step_stages(self, C, u1, u2, dt=0.0, dt_dev=None, ws=None, stream=None):
+        ws = self.workspace("step") if ws is None else ws
+        _check(self._lib.dg_rk_step_stages(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None,
+                                           _ptr(u1), _ptr(u2), _ptr(ws), _stream(stream)))
+        return C
+
+    def rk_step_vjp(self, C, ubar, dt=0.0, dt_dev=None, u1=None, u2=None, out=None, ws=None, stream=None):
+        import torch
+
+        out = self.empty_state() if out is None else out
+        if ws is None:
+            if getattr(self, "_ws_vjp", None) is None:
+                self._ws_vjp = torch.empty(self.info.ws_vjp, dtype=torch.uint8, device=self.device)
+            ws = self._ws_vjp
+        _check(self._lib.dg_rk_step_vjp(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None,
+                                        _ptr(u1) if u1 is not None else None, _ptr(u2) if u2 is not None else None,
+                                        _ptr(ubar), _ptr(out), _ptr(ws), _stream(stream)))
+        return out
+
+    def eval_points(self, C, out=None, stream=None):
+        import torch
+
+        out = torch.empty((self.n, self.nq, 4), dtype=torch.float64, device=self.device) if out is None else out
+        _check(self._lib.dg_eval_points(self._h, _ptr(C), _ptr(out), _stream(stream)))
+        return out
+
+    def quad_weights(self, out=None, stream=None):
+        import torch
+
+        out = torch.empty((self.n, self.nq), dtype=torch.float64, device=self.device) if out is None else out
+        _check(self._lib.dg_quad_weights(self._h, _ptr(out), _stream(stream)))
+        return out
 
     def rk_step(self, C, dt=0.0, dt_dev=None, prec=DG_FP64, ws=None, stream=None):
         ws = self.workspace("step") if ws is None else ws

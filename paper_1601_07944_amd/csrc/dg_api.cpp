@@ -17,9 +17,10 @@
 struct dg_mesh_s {
     dgk::MeshDev dev;
     dgh::TableLayout lay;
-    int64_t ws_rhs = 0, ws_step = 0;
+    int64_t ws_rhs = 0, ws_step = 0, ws_vjp = 0;
     // workspace offsets (bytes)
     size_t off_T0 = 0, off_T1 = 0, off_S = 0, off_part = 0, off_u1 = 0, off_u2 = 0;
+    size_t state_bytes = 0;
     std::vector<void*> allocs;
     // per-launch event timing (dg_timing_*)
     int surface = DG_SURFACE_ELEMENTWISE;
@@ -303,6 +304,8 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     m->off_u1 = 3 * trace + part;
     m->off_u2 = 3 * trace + part + state;
     m->ws_step = (int64_t)(3 * trace + part + 2 * state);
+    m->state_bytes = state;
+    m->ws_vjp = (int64_t)(4 * state);
     *out = m;
     return ok();
 }
@@ -334,6 +337,7 @@ int dg_mesh_info(dg_mesh m, dg_info* out)
     out->state_len = (int64_t)m->dev.npad * 4 * m->dev.np;
     out->ws_rhs = m->ws_rhs;
     out->ws_step = m->ws_step;
+    out->ws_vjp = m->ws_vjp;
     return ok();
 }
 
@@ -471,6 +475,68 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
     timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, T0, S, s); });
     timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 3, u2, C, C, S, dt, dt_dev, nullptr, s); });
     return check_launch("dg_rk_step");
+}
+
+int dg_rhs_vjp(dg_mesh m, const double* C, const double* Rb, double* Cb, void* ws, void* stream)
+{
+    if (!m || !C || !Rb || !Cb) return fail(DG_EINVAL, "null argument");
+    (void)ws;
+    hipStream_t s = (hipStream_t)stream;
+    timed(m, DG_KERNEL_VJP, s,
+          [&] { dgk::launch_stage_vjp(m->dev, 0, C, Rb, nullptr, nullptr, Cb, 1.0, nullptr, s); });
+    return check_launch("dg_rhs_vjp");
+}
+
+int dg_rk_step_stages(dg_mesh m, double* C, double dt, const double* dt_dev, double* u1, double* u2, void* ws,
+                      void* stream)
+{
+    if (!m || !C || !u1 || !u2) return fail(DG_EINVAL, "null argument");
+    (void)ws;
+    hipStream_t s = (hipStream_t)stream;
+    const dgk::MeshDev& d = m->dev;
+    timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, false, C, nullptr, u1, dt, dt_dev, s); });
+    timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, false, u1, C, u2, dt, dt_dev, s); });
+    timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, false, u2, nullptr, C, dt, dt_dev, s); });
+    return check_launch("dg_rk_step_stages");
+}
+
+int dg_rk_step_vjp(dg_mesh m, const double* C, double dt, const double* dt_dev, const double* u1_in,
+                   const double* u2_in, const double* ub, double* Cb, void* ws, void* stream)
+{
+    if (!m || !C || !ub || !Cb || !ws) return fail(DG_EINVAL, "null argument");
+    if ((u1_in == nullptr) != (u2_in == nullptr)) return fail(DG_EINVAL, "pass both stage states or neither");
+    hipStream_t s = (hipStream_t)stream;
+    const dgk::MeshDev& d = m->dev;
+    char* w = (char*)ws;
+    double* u1 = (double*)(w);
+    double* u2 = (double*)(w + m->state_bytes);
+    double* u2b = (double*)(w + 2 * m->state_bytes);
+    double* u1b = (double*)(w + 3 * m->state_bytes);
+    if (u1_in) {
+        u1 = const_cast<double*>(u1_in);
+        u2 = const_cast<double*>(u2_in);
+    } else {
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, false, C, nullptr, u1, dt, dt_dev, s); });
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, false, u1, C, u2, dt, dt_dev, s); });
+    }
+    timed(m, DG_KERNEL_VJP, s, [&] { dgk::launch_stage_vjp(d, 1, u2, ub, nullptr, nullptr, u2b, dt, dt_dev, s); });
+    timed(m, DG_KERNEL_VJP, s, [&] { dgk::launch_stage_vjp(d, 2, u1, u2b, nullptr, nullptr, u1b, dt, dt_dev, s); });
+    timed(m, DG_KERNEL_VJP, s, [&] { dgk::launch_stage_vjp(d, 3, C, u1b, ub, u2b, Cb, dt, dt_dev, s); });
+    return check_launch("dg_rk_step_vjp");
+}
+
+int dg_eval_points(dg_mesh m, const double* C, double* u, void* stream)
+{
+    if (!m || !C || !u) return fail(DG_EINVAL, "null argument");
+    dgk::launch_eval_points(m->dev, C, u, (hipStream_t)stream);
+    return check_launch("dg_eval_points");
+}
+
+int dg_quad_weights(dg_mesh m, double* w, void* stream)
+{
+    if (!m || !w) return fail(DG_EINVAL, "null argument");
+    dgk::launch_quad_weights(m->dev, w, (hipStream_t)stream);
+    return check_launch("dg_quad_weights");
 }
 
 int dg_set_surface_mode(dg_mesh m, int mode)

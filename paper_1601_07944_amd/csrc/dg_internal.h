@@ -63,6 +63,11 @@ void launch_element(const MeshDev& m, int mode, const double* C, const double* U
 // (it is the stage-0 state) and U0 must be nullptr
 void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out, double dt,
                   const double* dt_dev, hipStream_t s);
+// adjoint of the fused right-hand side / RK stages (modes of k_stage_vjp)
+void launch_stage_vjp(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X, const double* Y,
+                      double* out, double dt, const double* dt_dev, hipStream_t s);
+void launch_eval_points(const MeshDev& m, const double* C, double* u, hipStream_t s);
+void launch_quad_weights(const MeshDev& m, double* w, hipStream_t s);
 void launch_dt(const MeshDev& m, const double* C, double cfl, double* partial, double* dt_dev, hipStream_t s);
 int dt_partials(const MeshDev& m);
 void launch_pack(const MeshDev& m, const double* Cu, double* C, hipStream_t s);

@@ -448,6 +448,250 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
         }
 }
 
+// ---------------------------------------------------------------- adjoint
+// Cotangent of s = Fx(U).X + Fy(U).Y with respect to U (X, Y: cotangents of
+// the x and y fluxes).  With Ku = X0 rho + X1 mx + X2 my + X3 (E+p), Kv the
+// same with Y, and Pp = X1 + Y2 + u X3 + v Y3:
+//   d/d rho = -(Ku u + Kv v)/rho + u X0 + v Y0 + Pp (gamma-1) |v|^2/2
+//   d/d mx  = Ku/rho + u X1 + v Y1 - Pp (gamma-1) u
+//   d/d my  = Kv/rho + u X2 + v Y2 - Pp (gamma-1) v
+//   d/d E   = u X3 + v Y3 + Pp (gamma-1)
+// The normal flux F.n is the case X = n_x Fb, Y = n_y Fb.
+__device__ __forceinline__ void flux_vjp(double gm1, const double U[4], const double X[4], const double Y[4], double Ub[4])
+{
+    const double ri = 1.0 / U[0];
+    const double u = U[1] * ri, v = U[2] * ri;
+    const double p = gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
+    const double H = U[3] + p;
+    const double Ku = X[0] * U[0] + X[1] * U[1] + X[2] * U[2] + X[3] * H;
+    const double Kv = Y[0] * U[0] + Y[1] * U[1] + Y[2] * U[2] + Y[3] * H;
+    const double Pp = X[1] + Y[2] + u * X[3] + v * Y[3];
+    Ub[0] += -(Ku * u + Kv * v) * ri + u * X[0] + v * Y[0] + Pp * gm1 * 0.5 * (u * u + v * v);
+    Ub[1] += Ku * ri + u * X[1] + v * Y[1] - Pp * gm1 * u;
+    Ub[2] += Kv * ri + u * X[2] + v * Y[2] - Pp * gm1 * v;
+    Ub[3] += u * X[3] + v * Y[3] + Pp * gm1;
+}
+
+// Cotangent of the local Lax-Friedrichs flux with respect to its left
+// state: 1/2 A_n(UL)^T Fb + lambda/2 Fb - (sum_m Fb_m (UR_m - UL_m))/2
+// d lambda_L/d UL, the last term only when lambda_L >= lambda_R (ties take
+// the left branch); d lambda_L = sign(vn) d vn + d c, sign(0) = +1, and
+// d c = c/(2p) d p - c/(2 rho) d rho.
+__device__ __forceinline__ void llf_vjp_left(double gamma, double gm1, const double UL[4], const double UR[4], double nx,
+                                             double ny, const double Fb[4], double Ub[4])
+{
+    const double riL = 1.0 / UL[0], riR = 1.0 / UR[0];
+    const double uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
+    const double pL = gm1 * (UL[3] - 0.5 * (UL[1] * uL + UL[2] * vL));
+    const double pR = gm1 * (UR[3] - 0.5 * (UR[1] * uR + UR[2] * vR));
+    const double vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
+    const double cL = sqrt(gamma * pL * riL), cR = sqrt(gamma * pR * riR);
+    const double lamL = fabs(vnL) + cL, lamR = fabs(vnR) + cR;
+    const double lam = fmax(lamL, lamR);
+    double X[4], Y[4], jump = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        X[m] = 0.5 * nx * Fb[m];
+        Y[m] = 0.5 * ny * Fb[m];
+        Ub[m] += 0.5 * lam * Fb[m];
+        jump += Fb[m] * (UR[m] - UL[m]);
+    }
+    flux_vjp(gm1, UL, X, Y, Ub);
+    if (lamL >= lamR) {
+        const double lb = -0.5 * jump;
+        const double sv = vnL >= 0.0 ? lb : -lb;  // cotangent of vn
+        const double pb = lb * cL / (2.0 * pL);   // cotangent of p through c
+        Ub[0] += -sv * vnL * riL - lb * cL * riL * 0.5 + pb * gm1 * 0.5 * (uL * uL + vL * vL);
+        Ub[1] += sv * nx * riL - pb * gm1 * uL;
+        Ub[2] += sv * ny * riL - pb * gm1 * vL;
+        Ub[3] += pb * gm1;
+    }
+}
+
+// Vector-Jacobian product of the fused right-hand side, element-wise in
+// gather form.  For element i the cotangent of its side trace at point k is
+//   J_L(U_i, U_nb, n_i)^T (Fb_i(q, k) - Fb_nb(qn, p-k)),
+// because the neighbour's flux on the shared edge is F(U_nb, U_i, -n_i) =
+// -F(U_i, U_nb, n_i); Fb = -l omega_k (trace of Rbar/det J) on each side.
+// So no cotangent is scattered into another element.
+//   MODE 0: out = J(C)^T Rb
+//   MODE 1: out = 2/3 Rb + 2/3 dt J(C)^T Rb          (adjoint of RK stage 3)
+//   MODE 2: out = 1/4 Rb + 1/4 dt J(C)^T Rb          (adjoint of RK stage 2)
+//   MODE 3: out = 1/3 X + 3/4 Y + Rb + dt J(C)^T Rb  (adjoint of RK stage 1)
+template <int P, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_stage_vjp(int n, int npad, const double* __restrict__ C,
+                                                     const double* __restrict__ Rb, const double* __restrict__ X,
+                                                     const double* __restrict__ Y, double* __restrict__ out,
+                                                     const double* __restrict__ geo, const int* __restrict__ snb,
+                                                     const int* __restrict__ sside, const double* __restrict__ sgeo,
+                                                     const double* __restrict__ tab, double gamma, double dt,
+                                                     const double* __restrict__ dt_dev)
+{
+    using O = Ord<P>;
+    constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
+    constexpr int SS = (NE * NP) | 1;
+    __shared__ double phs[3 * SS];
+    for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) phs[(i / (NE * NP)) * SS + i % (NE * NP)] = tab[O::PHS + i];
+    __syncthreads();
+
+    const int e = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (e >= npad) return;
+    const int so = state_off(e, 4 * NP);
+    if (e >= n) {
+#pragma unroll
+        for (int x = 0; x < 4 * NP; ++x) out[so + x * LANES] = 0.0;
+        return;
+    }
+    const double gm1 = gamma - 1.0;
+    const double* g = geo + state_off(e, 6);
+    const double a00 = g[0], a01 = g[LANES], a10 = g[2 * LANES], a11 = g[3 * LANES], idet = g[4 * LANES];
+
+    double c[4][NP], rs[4][NP], cb[4][NP];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            c[m][j] = C[so + (m * NP + j) * LANES];
+            rs[m][j] = idet * Rb[so + (m * NP + j) * LANES];
+            cb[m][j] = 0.0;
+        }
+
+    // volume: Grb = sum_j w dphi/dr Rs, Gsb likewise; Fxb = adj^T (Grb, Gsb)
+#pragma unroll 1
+    for (int k = 0; k < NQ; ++k) {
+        double U[4], Xb[4], Yb[4], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double u = 0.0, gr = 0.0, gs = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                u = fma(tab[O::PHI + k * NP + j], c[m][j], u);
+                gr = fma(tab[O::DRW + k * NP + j], rs[m][j], gr);
+                gs = fma(tab[O::DSW + k * NP + j], rs[m][j], gs);
+            }
+            U[m] = u;
+            Xb[m] = a00 * gr + a10 * gs;
+            Yb[m] = a01 * gr + a11 * gs;
+        }
+        flux_vjp(gm1, U, Xb, Yb, Ub);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cb[m][j] = fma(tab[O::PHI + k * NP + j], Ub[m], cb[m][j]);
+    }
+
+    // surface
+    const int sides = sside[state_off(e, 1)];
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        const int nb = snb[state_off(e, 3) + q * LANES];
+        const int qn = (sides >> (2 * q)) & 3;
+        const int go = state_off(e, 9) + 3 * q * LANES;
+        const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
+        const double idn = geo[state_off(nb, 6) + 4 * LANES];
+        double UR[NE][4], RR[NE][4];
+#pragma unroll
+        for (int k = 0; k < NE; ++k)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) UR[k][m] = RR[k][m] = 0.0;
+        const int nbo = state_off(nb, 4 * NP);
+        const double* tq = phs + qn * SS;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            double cv[4], rv[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                cv[m] = C[nbo + (m * NP + j) * LANES];
+                rv[m] = idn * Rb[nbo + (m * NP + j) * LANES];
+            }
+#pragma unroll
+            for (int k = 0; k < NE; ++k) {
+                const double t = tq[(NE - 1 - k) * NP + j];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    UR[k][m] = fma(t, cv[m], UR[k][m]);
+                    RR[k][m] = fma(t, rv[m], RR[k][m]);
+                }
+            }
+        }
+#pragma unroll 1
+        for (int k = 0; k < NE; ++k) {
+            const double* tl = tab + O::PHS + (q * NE + k) * NP;
+            double UL[4], Fb[4], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+            const double w = -hl * tab[O::GW + k];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                double u = 0.0, r = 0.0;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    u = fma(tl[j], c[m][j], u);
+                    r = fma(tl[j], rs[m][j], r);
+                }
+                UL[m] = u;
+                Fb[m] = w * (r - RR[k][m]);
+            }
+            llf_vjp_left(gamma, gm1, UL, UR[k], nx, ny, Fb, Ub);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) cb[m][j] = fma(tl[j], Ub[m], cb[m][j]);
+        }
+    }
+
+    const double h = MODE == 0 ? 1.0 : (dt_dev ? dt_dev[0] : dt);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int x = so + (m * NP + j) * LANES;
+            if constexpr (MODE == 0) {
+                out[x] = cb[m][j];
+            } else if constexpr (MODE == 1) {
+                out[x] = (2.0 / 3.0) * Rb[x] + (2.0 / 3.0) * (h * cb[m][j]);
+            } else if constexpr (MODE == 2) {
+                out[x] = 0.25 * Rb[x] + 0.25 * (h * cb[m][j]);
+            } else {
+                out[x] = (1.0 / 3.0) * X[x] + 0.75 * Y[x] + Rb[x] + h * cb[m][j];
+            }
+        }
+}
+
+// U_h at the volume points, user order [N][NQ][4] (a1 on its own, for
+// functionals of the solution)
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_eval_points(int n, const int* __restrict__ perm, const double* __restrict__ C,
+                                                       double* __restrict__ u, const double* __restrict__ tab)
+{
+    using O = Ord<P>;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= n) return;
+    const int so = state_off(e, 4 * O::NP);
+    double* o = u + (size_t)perm[e] * O::NQ * 4;
+    for (int k = 0; k < O::NQ; ++k)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < O::NP; ++j) s = fma(tab[O::PHI + k * O::NP + j], C[so + (m * O::NP + j) * LANES], s);
+            o[k * 4 + m] = s;
+        }
+}
+
+// physical quadrature weights det J_i * w_k, user order [N][NQ]
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_quad_weights(int n, const int* __restrict__ perm,
+                                                        const double* __restrict__ vtx, double* __restrict__ wq,
+                                                        const double* __restrict__ tab)
+{
+    using O = Ord<P>;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= n) return;
+    const double* v = vtx + (size_t)e * 6;
+    const double det = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
+    double* o = wq + (size_t)perm[e] * O::NQ;
+    for (int k = 0; k < O::NQ; ++k) o[k] = det * tab[O::QW + k];
+}
+
 // ---------------------------------------------------------------- CFL step
 // dt = cfl * min_i r_i / (|v_i| + c_i) over cell averages sqrt(2) c_{i,0};
 // a non-physical or NaN mean makes the result NaN.  min is exact, so the
@@ -582,6 +826,30 @@ struct Launch {
             }
         }
 #undef DG_STAGE
+    }
+    static void stage_vjp(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X,
+                          const double* Y, double* out, double dt, const double* dt_dev, hipStream_t s)
+    {
+        const int nb = (m.npad + BLOCK - 1) / BLOCK;
+        dim3 g((nb + 7) / 8 * 8);
+#define DG_VJP(MODE)                                                                                             \
+    k_stage_vjp<P, MODE><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, Rb, X, Y, out, m.geo, m.side_nb, m.side_q, m.side_g, \
+                                             m.tab, m.gamma, dt, dt_dev)
+        switch (mode) {
+        case 0: DG_VJP(0); break;
+        case 1: DG_VJP(1); break;
+        case 2: DG_VJP(2); break;
+        default: DG_VJP(3); break;
+        }
+#undef DG_VJP
+    }
+    static void eval_points(const MeshDev& m, const double* C, double* u, hipStream_t s)
+    {
+        k_eval_points<P><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, m.perm, C, u, m.tab);
+    }
+    static void quad_weights(const MeshDev& m, double* w, hipStream_t s)
+    {
+        k_quad_weights<P><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, m.perm, m.vtx, w, m.tab);
     }
     static void dt_partial(const MeshDev& m, const double* C, double* partial, hipStream_t s)
     {

@@ -74,6 +74,19 @@ void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const
     DG_DISPATCH_P(m.p, stage(m, mode, mixed, C, U0, out, dt, dt_dev, s));
 }
 
+void launch_stage_vjp(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X, const double* Y,
+                      double* out, double dt, const double* dt_dev, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, stage_vjp(m, mode, C, Rb, X, Y, out, dt, dt_dev, s));
+}
+
+void launch_eval_points(const MeshDev& m, const double* C, double* u, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, eval_points(m, C, u, s));
+}
+
+void launch_quad_weights(const MeshDev& m, double* w, hipStream_t s) { DG_DISPATCH_P(m.p, quad_weights(m, w, s)); }
+
 int dt_partials(const MeshDev& m) { return (m.n + BLOCK - 1) / BLOCK; }
 
 void launch_dt(const MeshDev& m, const double* C, double cfl, double* partial, double* dt_dev, hipStream_t s)
