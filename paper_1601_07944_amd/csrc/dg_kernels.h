@@ -73,10 +73,14 @@ __device__ __forceinline__ void euler_flux(T gm1, const T U[4], T Fx[4], T Fy[4]
 // Local Lax-Friedrichs flux across unit normal n (from L to R):
 // Fn = (F(UL).n + F(UR).n)/2 - lambda/2 (UR - UL),
 // lambda = max(|vL.n| + cL, |vR.n| + cR).  Exchanging L and R and negating n
-// negates Fn bitwise.
+// negates Fn bitwise.  Contraction into fused multiply-adds is off here: a
+// product fused into the sum F(UL).n + F(UR).n on one side of an edge but not
+// on the other would break that symmetry (and exact conservation) at the
+// level of the rounding unit, which in FP32 is 6e-8.
 template <typename T>
 __device__ __forceinline__ void llf(T gamma, T gm1, const T UL[4], const T UR[4], T nx, T ny, T Fn[4])
 {
+#pragma clang fp contract(off)
     const T riL = T(1) / UL[0], riR = T(1) / UR[0];
     const T uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
     const T pL = gm1 * (UL[3] - T(0.5) * (UL[1] * uL + UL[2] * vL));
