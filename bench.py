@@ -103,6 +103,89 @@ def cpu_baseline(mesh, p, seconds: float):
     }
 
 
+def run_scale(args):
+    """Per-order throughput at scale (one JSON line with a list): periodic
+    unit square, density jump across r < 0.25 about (0.5, 0.5) on the smooth
+    density wave (u = v = 0.5, p = 1), FP64 and mixed precision, K steps
+    each; the stage kernel's algorithmic bytes per launch over its mean
+    launch time against the HBM peak."""
+    import numpy as np
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+    from paper_1601_07944_amd import workloads as W
+
+    B.load()
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    if args.mesh == "delaunay":
+        mesh = W.delaunay_mesh(args.n_tri // 2, 4)
+    else:
+        n = int(round((args.n_tri / 2) ** 0.5))
+        mesh = W.square_mesh(n, 1.0, 0.2, 4)
+    t_mesh = time.perf_counter() - t0
+    print(f"[scale] mesh {mesh.name}: {mesh.n_elem} triangles in {t_mesh:.1f} s", file=sys.stderr, flush=True)
+    res = []
+    for p in [int(x) for x in args.orders.split(",")]:
+        dm = B.DGMesh.from_mesh(mesh, p)
+        xy = dm.quad_points().cpu().numpy()
+        C0 = dm.project(torch.from_numpy(np.ascontiguousarray(W.density_jump(xy[..., 0], xy[..., 1]))).to(dev))
+        del xy
+        ws = dm.workspace("step")
+        dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
+        cfl = 0.3 / (2 * p + 1)
+        dof = dm.n * dm.np * 4
+        row = {"p": p, "n_elem": dm.n, "dof": dof}
+        for name, prec in (("fp64", B.DG_FP64), ("mixed", B.DG_MIXED)):
+            C = C0.clone()
+
+            def step():
+                dm.max_dt(C, cfl, dt_dev=dt_dev, to_host=False, ws=ws)
+                dm.rk_step(C, dt_dev=dt_dev, prec=prec, ws=ws)
+
+            for _ in range(3):
+                step()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            dm.timing(True)
+            for _ in range(min(args.steps, 10)):
+                step()
+            torch.cuda.synchronize()
+            dm.timing(False)
+            kt = dm.timing_read()
+            st_ms = kt["stage"][0] / kt["stage"][1]
+            ach = algorithmic_bytes_stage_kernel(dm.n, dm.np, 2.0 / 3.0) / (st_ms * 1e-3) / 1e9
+            row[name] = {
+                "value": dof * 3 / (ms * 1e-3),
+                "ms_per_step": ms,
+                "stage_ms": st_ms,
+                "dt_ms": kt["dt"][0] / max(1, kt["dt"][1]),
+                "stage_hbm_GBs_algorithmic": ach,
+                "frac_hbm": ach / HBM_PEAK_GBS,
+            }
+            print(f"[scale] p={p} {name}: {row[name]}", file=sys.stderr, flush=True)
+            del C
+        row["mixed_speedup"] = row["fp64"]["ms_per_step"] / row["mixed"]["ms_per_step"]
+        res.append(row)
+        dm.close()
+        del C0, ws
+        torch.cuda.empty_cache()
+    out = {
+        "workload": f"density jump on the smooth wave, periodic unit square, {mesh.n_elem} triangles ({args.mesh}), "
+        f"SSP-RK3 steps with device CFL step",
+        "steps": args.steps,
+        "orders": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +199,11 @@ def main():
         help="for rocprofv3 --pmc runs: a few steps of the workload, then a 256 MiB device copy of known size "
         "(the calibration kernel for FETCH_SIZE / WRITE_SIZE); prints nothing else",
     )
+    ap.add_argument("--workload", choices=["vortex", "scale"], default="vortex",
+                    help="vortex: the 32,768-triangle p=3 headline workload (default); scale: per-order sweep at scale")
+    ap.add_argument("--mesh", choices=["square", "delaunay"], default="square", help="scale workload mesh")
+    ap.add_argument("--n-tri", type=int, default=4_000_000, help="scale workload triangles")
+    ap.add_argument("--orders", default="1,2,3,4,5", help="scale workload orders")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(
@@ -124,6 +212,10 @@ def main():
             file=sys.stderr,
         )
         sys.exit(2)
+
+    if args.workload == "scale":
+        run_scale(args)
+        return
 
     import numpy as np
     import torch

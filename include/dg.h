@@ -108,6 +108,10 @@ int dg_mesh_validate(int p, int64_t n_elem, const double* vxy, const int64_t* nb
  *   nbr_side  host [n_elem][3]: that neighbour's local side index;
  *   gamma     ratio of specific heats (1.4 for air);
  *   out       receives the handle.
+ * Validation: det J > 0; neighbours point back; the two copies of every
+ * edge are the same segment in opposite directions to within 1e-12 times
+ * the larger of its length and its vertices' coordinate magnitude (periodic
+ * copies carry the rounding of shifted coordinates).
  * Validates first (see dg_mesh_validate), then builds the edge list (one
  * entry per edge, left = lower internal id, normal from left to right),
  * geometry (adj(J), 1/det J, inscribed radius; per-edge unit normal and

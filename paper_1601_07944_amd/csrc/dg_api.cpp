@@ -122,8 +122,13 @@ int dg_mesh_validate(int p, int64_t n, const double* vxy, const int64_t* nbr, co
             const double* w = vxy + 6 * j;
             double ex = v[2 * ((q + 1) % 3)] - v[2 * q], ey = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
             double fx = w[2 * ((qn + 1) % 3)] - w[2 * qn], fy = w[2 * ((qn + 1) % 3) + 1] - w[2 * qn + 1];
+            // tolerance: a periodic copy carries the rounding of the shifted
+            // coordinates, which scales with their magnitude, not the length
             double len = std::sqrt(ex * ex + ey * ey);
-            if (std::fabs(ex + fx) > 1e-12 * len || std::fabs(ey + fy) > 1e-12 * len)
+            double mag = 0.0;
+            for (int c = 0; c < 6; ++c) mag = std::fmax(mag, std::fmax(std::fabs(v[c]), std::fabs(w[c])));
+            const double tol = 1e-12 * std::fmax(len, mag);
+            if (std::fabs(ex + fx) > tol || std::fabs(ey + fy) > tol)
                 return fail(DG_EMESH, "element %lld side %d and element %lld side %d are not the same edge",
                             (long long)i, q, (long long)j, qn);
         }
