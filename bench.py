@@ -136,7 +136,9 @@ def run_scale(args):
         cfl = 0.3 / (2 * p + 1)
         dof = dm.n * dm.np * 4
         row = {"p": p, "n_elem": dm.n, "dof": dof}
-        for name, prec in (("fp64", B.DG_FP64), ("mixed", B.DG_MIXED)):
+        for name, prec, lanes in (("fp64", B.DG_FP64, 0), ("mixed", B.DG_MIXED, 0), ("fp64_lanes1", B.DG_FP64, 1),
+                                  ("fp64_lanes4", B.DG_FP64, 4)):
+            dm.set_lanes(lanes)
             C = C0.clone()
 
             def step():
@@ -367,6 +369,20 @@ def main():
     torch.cuda.synchronize()
     ms_vjp = e0.elapsed_time(e1)
 
+    # the other element-wise variant (1 or 4 work-items per element)
+    lanes_alt = 1 if dm.info.n_elem <= 1048576 else 4
+    dm.set_lanes(lanes_alt)
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step_alt = e0.elapsed_time(e1) / args.steps
+    dm.set_lanes(0)
+
     # the paper's edge-wise organisation (3 kernels per RHS), same steps
     dm.set_surface_mode(dm.SURFACE_EDGEWISE)
     for _ in range(5):
@@ -413,6 +429,8 @@ def main():
         "kernels": kernels,
         "ms_per_step_with_kernel_events": ms_step_events,
         "surface_edgewise": {"ms_per_step": ms_step_edge, "value": dof * 3 / (ms_step_edge * 1e-3)},
+        "lanes_per_element": {"headline": 4 if dm.info.n_elem <= 1048576 else 1, "alternative": lanes_alt,
+                              "alternative_ms_per_step": ms_step_alt},
         "wall_s_timed_region": wall,
         "rhs_only": {"value": dof / (ms_rhs * 1e-3), "unit": "DOF-updates/s", "ms_per_call": ms_rhs},
         "mixed": {

@@ -214,6 +214,17 @@ int dg_quad_weights(dg_mesh m, double* w_dev, void* stream);
 enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1 };
 int dg_set_surface_mode(dg_mesh m, int mode);
 
+/* Work-items per element in the element-wise kernels (forward right-hand
+ * side and RK stages): 1, or 4 (one lane per conserved variable; the
+ * variables of a point value are exchanged inside the quad of lanes).  Four
+ * lanes give four times as many wavefronts and a quarter of the registers
+ * per lane, at the price of recomputing a few flux scalars per lane; they
+ * pay off on meshes too small to fill the GPU.  0 = automatic (4 lanes up
+ * to DG_LANES4_MAX_ELEMENTS elements, else 1).  Both give the same result
+ * to rounding. */
+#define DG_LANES4_MAX_ELEMENTS 1048576
+int dg_set_lanes_per_element(dg_mesh m, int lanes);
+
 /* Per-kernel timing (the paper's kernel runtime distribution, measured with
  * events around every launch).  dg_timing_enable(m, 1) makes every later
  * launch for this mesh record a pair of HIP events on its stream;

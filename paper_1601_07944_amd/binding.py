@@ -48,6 +48,7 @@ EXPORTS = [
     "dg_rk_step_stages",
     "dg_eval_points",
     "dg_quad_weights",
+    "dg_set_lanes_per_element",
     "dg_set_surface_mode",
     "dg_timing_enable",
     "dg_timing_read",
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH):
     lib.dg_rk_step_stages.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
     lib.dg_eval_points.argtypes = [_vp, _vp, _vp, _vp]
     lib.dg_quad_weights.argtypes = [_vp, _vp, _vp]
+    lib.dg_set_lanes_per_element.argtypes = [_vp, i32]
     lib.dg_set_surface_mode.argtypes = [_vp, i32]
     lib.dg_timing_enable.argtypes = [_vp, i32]
     lib.dg_timing_read.argtypes = [_vp, _dp, ctypes.POINTER(i64), i32]
@@ -280,6 +282,10 @@ class DGMesh:
     KERNELS = ("traces", "edge", "element", "dt", "stage", "vjp")
     SURFACE_ELEMENTWISE = 0
     SURFACE_EDGEWISE = 1
+
+    def set_lanes(self, lanes: int):
+        """Work-items per element in the element-wise kernels: 0 (auto), 1 or 4."""
+        _check(self._lib.dg_set_lanes_per_element(self._h, int(lanes)))
 
     def set_surface_mode(self, mode: int):
         _check(self._lib.dg_set_surface_mode(self._h, int(mode)))

@@ -284,6 +284,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.npad = npad;
     d.nedge = nedge;
     d.gamma = gamma;
+    d.lanes4 = N <= DG_LANES4_MAX_ELEMENTS;
     d.tab = (const double*)d_tab;
     d.tab32 = (const float*)d_tab32;
     d.geo = (const double*)d_geo;
@@ -542,6 +543,14 @@ int dg_quad_weights(dg_mesh m, double* w, void* stream)
     if (!m || !w) return fail(DG_EINVAL, "null argument");
     dgk::launch_quad_weights(m->dev, w, (hipStream_t)stream);
     return check_launch("dg_quad_weights");
+}
+
+int dg_set_lanes_per_element(dg_mesh m, int lanes)
+{
+    if (!m) return fail(DG_EINVAL, "null mesh");
+    if (lanes != 0 && lanes != 1 && lanes != 4) return fail(DG_EINVAL, "lanes per element must be 0, 1 or 4");
+    m->dev.lanes4 = lanes == 4 || (lanes == 0 && m->dev.n <= DG_LANES4_MAX_ELEMENTS);
+    return ok();
 }
 
 int dg_set_surface_mode(dg_mesh m, int mode)

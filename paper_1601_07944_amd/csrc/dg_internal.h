@@ -35,6 +35,7 @@ struct MeshDev {
     int n = 0;         // real elements
     int npad = 0;      // padded to a multiple of 64
     int nedge = 0;
+    bool lanes4 = false;  // fused kernels: 4 lanes per element instead of 1
     double gamma = 1.4;
     const double* tab = nullptr;      // reference tables (TableLayout)
     const float* tab32 = nullptr;     // the same tables rounded to FP32 (mixed precision)

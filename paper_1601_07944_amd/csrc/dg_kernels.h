@@ -452,6 +452,163 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
         }
 }
 
+// ---------------------------------------------------------------- fused stage, 4 lanes per element
+// The same right-hand side and stage update as k_stage, with the element's
+// work spread over a quad of lanes: lane m of the quad owns variable m
+// (its N_p coefficients, its accumulators, its gathered neighbour values).
+// All lanes of a wavefront walk the same volume point or side, so every
+// table read is uniform (scalar loads); the four variables of a point value
+// or trace are exchanged inside the quad with DPP broadcasts, and the few
+// scalars of the flux (1/rho, p, the wave speed) are recomputed by each lane.
+// Per-lane registers drop from ~250 to ~100 and a mesh yields four times as
+// many wavefronts, which is what small meshes need to fill 256 CUs.
+
+// broadcast lane S of each quad to the whole quad
+template <int S>
+__device__ __forceinline__ double quad_bcast(double x)
+{
+    constexpr int ctrl = S * 0x55;  // quad_perm(S, S, S, S)
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int S>
+__device__ __forceinline__ float quad_bcast(float x)
+{
+    constexpr int ctrl = S * 0x55;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+
+template <int P, int MODE, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double* __restrict__ C,
+                                                  const double* __restrict__ U0, double* __restrict__ out,
+                                                  const double* __restrict__ geo, const int* __restrict__ snb,
+                                                  const int* __restrict__ sside, const double* __restrict__ sgeo,
+                                                  const T* __restrict__ tab, const double* __restrict__ tab64,
+                                                  double gamma, double dt, const double* __restrict__ dt_dev)
+{
+    using O = Ord<P>;
+    constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
+    constexpr int SS = (NE * NP) | 1;
+    constexpr bool F64 = sizeof(T) == sizeof(double);
+    __shared__ T phs[3 * SS];
+    for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) phs[(i / (NE * NP)) * SS + i % (NE * NP)] = tab[O::PHS + i];
+    __syncthreads();
+
+    // 64 elements per workgroup; every lane stays active until the stores
+    // (the quad exchanges read the neighbouring lanes)
+    const int e = xcd_block(blockIdx.x, gridDim.x) * (BLOCK / 4) + (threadIdx.x >> 2);
+    const int m = threadIdx.x & 3;
+    if (e >= npad) return;  // whole quads (and whole workgroups) leave together
+    const bool real = e < n;
+    const int so = state_off(e, 4 * NP) + m * NP * LANES;
+    const T s1 = T(m == 1), s2 = T(m == 2), s3 = T(m == 3);
+    const T gam = T(gamma), gm1 = T(gamma - 1.0);
+    const double* g = geo + state_off(e, 6);
+    const T a00 = T(g[0]), a01 = T(g[LANES]), a10 = T(g[2 * LANES]), a11 = T(g[3 * LANES]);
+    const double idet = g[4 * LANES];
+
+    T c[NP], acc[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        c[j] = T(C[so + j * LANES]);
+        acc[j] = T(0);
+    }
+    double acc0 = 0.0;
+
+    // volume integral, eq. (volume)
+#pragma unroll 1
+    for (int k = 0; k < NQ; ++k) {
+        T um = T(0);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) um = fma(tab[O::PHI + k * NP + j], c[j], um);
+        const T r0 = quad_bcast<0>(um), r1 = quad_bcast<1>(um), r2 = quad_bcast<2>(um), r3 = quad_bcast<3>(um);
+        const T ri = T(1) / r0;
+        const T u = r1 * ri, v = r2 * ri;
+        const T p = gm1 * (r3 - T(0.5) * (r1 * u + r2 * v));
+        // F_x = U u + p (0, 1, 0, u), F_y = U v + p (0, 0, 1, v)
+        const T Fx = um * u + p * (s1 + s3 * u);
+        const T Fy = um * v + p * (s2 + s3 * v);
+        const T gr = a00 * Fx + a01 * Fy;
+        const T gs = a10 * Fx + a11 * Fy;
+#pragma unroll
+        for (int j = 1; j < NP; ++j)
+            acc[j] = fma(tab[O::DRW + k * NP + j], gr, fma(tab[O::DSW + k * NP + j], gs, acc[j]));
+    }
+
+    // surface integral, eq. (surface)
+    const int sides = sside[state_off(e, 1)];
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        const int nb = snb[state_off(e, 3) + q * LANES];
+        const int qn = (sides >> (2 * q)) & 3;
+        const int go = state_off(e, 9) + 3 * q * LANES;
+        const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
+        const double hl = sgeo[go + 2 * LANES];
+        const int nbo = state_off(nb, 4 * NP) + m * NP * LANES;
+        T cn[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) cn[j] = T(C[nbo + j * LANES]);
+        const T* tq = phs + qn * SS;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const T* tl = tab + O::PHS + (q * NE + k) * NP;
+            T ul = T(0), ur = T(0);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                ul = fma(tl[j], c[j], ul);
+                ur = fma(tq[(NE - 1 - k) * NP + j], cn[j], ur);
+            }
+            T F;
+            {
+#pragma clang fp contract(off)
+                const T L0 = quad_bcast<0>(ul), L1 = quad_bcast<1>(ul), L2 = quad_bcast<2>(ul), L3 = quad_bcast<3>(ul);
+                const T R0 = quad_bcast<0>(ur), R1 = quad_bcast<1>(ur), R2 = quad_bcast<2>(ur), R3 = quad_bcast<3>(ur);
+                const T riL = T(1) / L0, riR = T(1) / R0;
+                const T uL = L1 * riL, vL = L2 * riL, uR = R1 * riR, vR = R2 * riR;
+                const T pL = gm1 * (L3 - T(0.5) * (L1 * uL + L2 * vL));
+                const T pR = gm1 * (R3 - T(0.5) * (R1 * uR + R2 * vR));
+                const T vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
+                const T lam = fmax(fabs(vnL) + sqrt(gam * pL * riL), fabs(vnR) + sqrt(gam * pR * riR));
+                // F.n = U vn + p (0, nx, ny, vn)
+                const T fl = ul * vnL + pL * (s1 * nx + s2 * ny + s3 * vnL);
+                const T fr = ur * vnR + pR * (s1 * nx + s2 * ny + s3 * vnR);
+                F = T(0.5) * (fl + fr) - T(0.5) * lam * (ur - ul);
+            }
+            const double w = -hl * tab64[O::GW + k];
+            acc0 = fma(w * tab64[O::PHS + (q * NE + k) * NP], double(F), acc0);
+            const T wf = T(w) * F;
+#pragma unroll
+            for (int j = 1; j < NP; ++j) acc[j] = fma(tl[j], wf, acc[j]);
+        }
+    }
+
+    if (!real) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) out[so + j * LANES] = 0.0;
+        return;
+    }
+    const double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int x = so + j * LANES;
+        const double L = idet * (j == 0 ? acc0 : double(acc[j]));
+        if constexpr (MODE == 0) {
+            out[x] = L;
+        } else {
+            const double cs = F64 ? double(c[j]) : C[x];
+            if constexpr (MODE == 1) {
+                out[x] = cs + h * L;
+            } else if constexpr (MODE == 2) {
+                out[x] = 0.75 * U0[x] + 0.25 * (cs + h * L);
+            } else {
+                out[x] = (1.0 / 3.0) * out[x] + (2.0 / 3.0) * (cs + h * L);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- adjoint
 // Cotangent of s = Fx(U).X + Fy(U).Y with respect to U (X, Y: cotangents of
 // the x and y fluxes).  With Ku = X0 rho + X1 mx + X2 my + X3 (E+p), Kv the
@@ -814,6 +971,29 @@ struct Launch {
 #define DG_STAGE(MODE, T, TAB)                                                                                  \
     k_stage<P, MODE, T><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, TAB, \
                                             m.tab, m.gamma, dt, dt_dev)
+        if (m.lanes4) {
+            dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
+#define DG_STAGE4(MODE, T, TAB)                                                                                  \
+    k_stage4<P, MODE, T><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, TAB, \
+                                              m.tab, m.gamma, dt, dt_dev)
+            if (mixed) {
+                switch (mode) {
+                case 0: DG_STAGE4(0, float, m.tab32); break;
+                case 1: DG_STAGE4(1, float, m.tab32); break;
+                case 2: DG_STAGE4(2, float, m.tab32); break;
+                default: DG_STAGE4(3, float, m.tab32); break;
+                }
+            } else {
+                switch (mode) {
+                case 0: DG_STAGE4(0, double, m.tab); break;
+                case 1: DG_STAGE4(1, double, m.tab); break;
+                case 2: DG_STAGE4(2, double, m.tab); break;
+                default: DG_STAGE4(3, double, m.tab); break;
+                }
+            }
+#undef DG_STAGE4
+            return;
+        }
         if (mixed) {
             switch (mode) {
             case 0: DG_STAGE(0, float, m.tab32); break;

@@ -37,19 +37,22 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def gpu_mesh(mesh, p):
+def gpu_mesh(mesh, p, lanes=0):
     from paper_1601_07944_amd import binding as B
 
-    return B.DGMesh.from_mesh(mesh, p)
+    dm = B.DGMesh.from_mesh(mesh, p)
+    dm.set_lanes(lanes)
+    return dm
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
-def test_mixed_rhs_bound(p):
+def test_mixed_rhs_bound(p, lanes):
     mesh = W.delaunay_mesh(900, 4)
     orc = O.Oracle(mesh, p)
     C = orc.project(W.density_jump)
-    dm = gpu_mesh(mesh, p)
-    case(f"dg_rhs DG_MIXED p={p} N={mesh.n_elem}")
+    dm = gpu_mesh(mesh, p, lanes)
+    case(f"dg_rhs DG_MIXED p={p} N={mesh.n_elem} lanes={lanes}")
     R = dm.unpack(dm.rhs(dm.pack(dev(C)), prec=MIXED)).cpu().numpy()
     ref = orc.rhs(C)
     err = rel_l2(R, ref)
@@ -60,15 +63,16 @@ def test_mixed_rhs_bound(p):
     assert np.all(np.abs(terms.sum(0)) < 1e-13 * np.abs(terms).sum(0))
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("p", [2, 4])
-def test_mixed_100_steps_smooth_unit_square(p):
+def test_mixed_100_steps_smooth_unit_square(p, lanes):
     # smooth density wave on a periodic Delaunay mesh of the unit square
     import torch
 
     mesh = W.delaunay_mesh(2000, 2)
     orc = O.Oracle(mesh, p)
     C0 = orc.project(W.smooth_density)
-    dm = gpu_mesh(mesh, p)
+    dm = gpu_mesh(mesh, p, lanes)
     Cg = dm.pack(dev(C0))
     cfl = 0.3 / (2 * p + 1)
     case(f"dg_rk_step DG_MIXED p={p} 100 steps N={mesh.n_elem}")

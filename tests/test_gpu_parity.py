@@ -28,14 +28,16 @@ def torch_mod():
 
 
 ELEMENTWISE, EDGEWISE = 0, 1
-SURFACE = {"elementwise": ELEMENTWISE, "edgewise": EDGEWISE}
+# surface organisation and work-items per element of the element-wise path
+SURFACE = {"elementwise1": (ELEMENTWISE, 1), "elementwise4": (ELEMENTWISE, 4), "edgewise": (EDGEWISE, 0)}
 
 
-def gpu_mesh(mesh, p, surface=ELEMENTWISE):
+def gpu_mesh(mesh, p, surface=(ELEMENTWISE, 0)):
     from paper_1601_07944_amd import binding as B
 
     dm = B.DGMesh.from_mesh(mesh, p)
-    dm.set_surface_mode(surface)
+    dm.set_surface_mode(surface[0])
+    dm.set_lanes(surface[1])
     return dm
 
 
@@ -56,7 +58,7 @@ def check_close(got, ref, tol=TOL):
     return err
 
 
-def gpu_rhs(mesh, p, C_user, surface=ELEMENTWISE):
+def gpu_rhs(mesh, p, C_user, surface=(ELEMENTWISE, 0)):
     dm = gpu_mesh(mesh, p, surface)
     C = dm.pack(to_dev(C_user))
     R = dm.rhs(C)
@@ -253,11 +255,13 @@ def test_surface_strategies_agree_and_conserve(p):
     orc = O.Oracle(mesh, p)
     C = W.random_state(mesh.n_elem, orc.np, seed=5)
     case(f"surface strategies p={p}")
-    a = gpu_rhs(mesh, p, C, ELEMENTWISE)
-    b = gpu_rhs(mesh, p, C, EDGEWISE)
+    a = gpu_rhs(mesh, p, C, SURFACE["elementwise1"])
+    b = gpu_rhs(mesh, p, C, SURFACE["edgewise"])
+    c = gpu_rhs(mesh, p, C, SURFACE["elementwise4"])
     check_close(a, b, 1e-13)
+    check_close(c, b, 1e-13)
     det = orc.det()
-    for R in (a, b):
+    for R in (a, b, c):
         terms = det[:, None] * R[:, :, 0]
         assert np.all(np.abs(terms.sum(0)) < 1e-13 * np.abs(terms).sum(0))
 
