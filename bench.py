@@ -141,24 +141,20 @@ def run_scale(args):
             dm.set_lanes(lanes)
             C = C0.clone()
 
-            def step():
-                dm.max_dt(C, cfl, dt_dev=dt_dev, to_host=False, ws=ws)
-                dm.rk_step(C, dt_dev=dt_dev, prec=prec, ws=ws)
+            def step(k=1):
+                dm.advance(C, k, cfl, dt_dev=dt_dev, prec=prec, ws=ws)
 
-            for _ in range(3):
-                step()
+            step(3)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             e0.record()
-            for _ in range(args.steps):
-                step()
+            step(args.steps)
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.steps
             dm.timing(True)
-            for _ in range(min(args.steps, 10)):
-                step()
+            step(min(args.steps, 10))
             torch.cuda.synchronize()
             dm.timing(False)
             kt = dm.timing_read()
@@ -168,7 +164,7 @@ def run_scale(args):
                 "value": dof * 3 / (ms * 1e-3),
                 "ms_per_step": ms,
                 "stage_ms": st_ms,
-                "dt_ms": kt["dt"][0] / max(1, kt["dt"][1]),
+                "dt_ms": (kt["dt"][0] / kt["dt"][1]) if kt["dt"][1] else 0.0,
                 "stage_hbm_GBs_algorithmic": ach,
                 "frac_hbm": ach / HBM_PEAK_GBS,
             }
@@ -239,9 +235,13 @@ def main():
     cfl = 0.3 / (2 * p + 1)
     dof = dm.n * dm.np * 4
 
+    def steps_prec(state, prec, k):
+        # k steps of the whole hot path: CFL step length on the device, then
+        # one SSP-RK3 step (three fused stages), in one library call
+        dm.advance(state, k, cfl, dt_dev=dt_dev, prec=prec, ws=ws)
+
     def step_prec(state, prec):
-        dm.max_dt(state, cfl, dt_dev=dt_dev, to_host=False, ws=ws)
-        dm.rk_step(state, dt_dev=dt_dev, prec=prec, ws=ws)
+        steps_prec(state, prec, 1)
 
     def step():
         step_prec(C, B.DG_FP64)
@@ -265,8 +265,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
-        step()
+    steps_prec(C, B.DG_FP64, args.steps)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -277,8 +276,7 @@ def main():
     dm.timing(True)
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
-        step()
+    steps_prec(C, B.DG_FP64, args.steps)
     e1.record()
     torch.cuda.synchronize()
     dm.timing(False)
@@ -319,13 +317,11 @@ def main():
     Cmx.copy_(C64)
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
-        step_prec(Cmx, B.DG_MIXED)
+    steps_prec(Cmx, B.DG_MIXED, args.steps)
     e1.record()
     torch.cuda.synchronize()
     ms_step_mixed = e0.elapsed_time(e1) / args.steps
-    for _ in range(args.steps):
-        step_prec(C64, B.DG_FP64)
+    steps_prec(C64, B.DG_FP64, args.steps)
     torch.cuda.synchronize()
     mixed_err = float(torch.linalg.norm(Cmx - C64) / torch.linalg.norm(C64))
 
@@ -370,14 +366,13 @@ def main():
     ms_vjp = e0.elapsed_time(e1)
 
     # the other element-wise variant (1 or 4 work-items per element)
-    lanes_alt = 1 if dm.info.n_elem <= 1048576 else 4
+    auto4 = dm.info.n_elem <= 1048576 or p >= 4
+    lanes_alt = 1 if auto4 else 4
     dm.set_lanes(lanes_alt)
-    for _ in range(5):
-        step()
+    steps_prec(C, B.DG_FP64, 5)
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
-        step()
+    steps_prec(C, B.DG_FP64, args.steps)
     e1.record()
     torch.cuda.synchronize()
     ms_step_alt = e0.elapsed_time(e1) / args.steps
@@ -385,12 +380,10 @@ def main():
 
     # the paper's edge-wise organisation (3 kernels per RHS), same steps
     dm.set_surface_mode(dm.SURFACE_EDGEWISE)
-    for _ in range(5):
-        step()
+    steps_prec(C, B.DG_FP64, 5)
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
-        step()
+    steps_prec(C, B.DG_FP64, args.steps)
     e1.record()
     torch.cuda.synchronize()
     ms_step_edge = e0.elapsed_time(e1) / args.steps
@@ -429,7 +422,7 @@ def main():
         "kernels": kernels,
         "ms_per_step_with_kernel_events": ms_step_events,
         "surface_edgewise": {"ms_per_step": ms_step_edge, "value": dof * 3 / (ms_step_edge * 1e-3)},
-        "lanes_per_element": {"headline": 4 if dm.info.n_elem <= 1048576 else 1, "alternative": lanes_alt,
+        "lanes_per_element": {"headline": 4 if auto4 else 1, "alternative": lanes_alt,
                               "alternative_ms_per_step": ms_step_alt},
         "wall_s_timed_region": wall,
         "rhs_only": {"value": dof / (ms_rhs * 1e-3), "unit": "DOF-updates/s", "ms_per_call": ms_rhs},

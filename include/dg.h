@@ -163,6 +163,19 @@ int dg_max_dt(dg_mesh m, const double* C_dev, double cfl, double* dt_dev, double
 int dg_rk_step(dg_mesh m, double* C_dev, double dt, const double* dt_dev, dg_precision prec, void* ws_dev,
                void* stream);
 
+/* nsteps SSP-RK3 steps in place, each with its own CFL step length taken
+ * from the state at the start of the step (the paper's host-directed time
+ * loop, Section "Time-stepping", kept on the device): the same results, bit
+ * for bit, as nsteps x { dg_max_dt(C, cfl, dt_dev); dg_rk_step(C, dt_dev) }.
+ * With the element-wise surface mode and 4 lanes per element the reduction
+ * is fused into the stage kernels (three launches per step).  dt_dev
+ * receives the last step's length; dt_hist_dev (may be NULL) receives all
+ * nsteps lengths.  A non-physical mean turns the step length into NaN (and
+ * the state into NaN); the call itself does not wait to check.
+ * ws: ws_step bytes. */
+int dg_advance(dg_mesh m, double* C_dev, int64_t nsteps, double cfl, double* dt_dev, double* dt_hist_dev,
+               dg_precision prec, void* ws_dev, void* stream);
+
 /* Adjoint (vector-Jacobian product) of dg_rhs, the derivative of the
  * discrete operator of eq. (2ddg0) transposed: Cbar = (dR/dC)^T Rbar, all
  * FP64, internal layout.  Element-wise gather form: no cotangent is
@@ -219,9 +232,10 @@ int dg_set_surface_mode(dg_mesh m, int mode);
  * variables of a point value are exchanged inside the quad of lanes).  Four
  * lanes give four times as many wavefronts and a quarter of the registers
  * per lane, at the price of recomputing a few flux scalars per lane; they
- * pay off on meshes too small to fill the GPU.  0 = automatic (4 lanes up
- * to DG_LANES4_MAX_ELEMENTS elements, else 1).  Both give the same result
- * to rounding. */
+ * pay off on meshes too small to fill the GPU, and at p >= 4, where one
+ * lane's registers cannot hold an element.  0 = automatic (4 lanes up to
+ * DG_LANES4_MAX_ELEMENTS elements or for p >= 4, else 1).  Both give the
+ * same result to rounding. */
 #define DG_LANES4_MAX_ELEMENTS 1048576
 int dg_set_lanes_per_element(dg_mesh m, int lanes);
 

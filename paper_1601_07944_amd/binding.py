@@ -43,6 +43,7 @@ EXPORTS = [
     "dg_rhs",
     "dg_max_dt",
     "dg_rk_step",
+    "dg_advance",
     "dg_rhs_vjp",
     "dg_rk_step_vjp",
     "dg_rk_step_stages",
@@ -105,6 +106,7 @@ def load(path: str = LIB_PATH):
     lib.dg_rhs.argtypes = [_vp, _vp, _vp, i32, _vp, _vp]
     lib.dg_max_dt.argtypes = [_vp, _vp, ctypes.c_double, _vp, _dp, _vp, _vp]
     lib.dg_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _vp, i32, _vp, _vp]
+    lib.dg_advance.argtypes = [_vp, _vp, i64, ctypes.c_double, _vp, _vp, i32, _vp, _vp]
     lib.dg_rhs_vjp.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.dg_rk_step_vjp.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.dg_rk_step_stages.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
@@ -300,6 +302,16 @@ class DGMesh:
         cnt = (ctypes.c_int64 * nk)()
         _check(self._lib.dg_timing_read(self._h, ms, cnt, nk))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
+
+    def advance(self, C, nsteps, cfl, dt_dev=None, dt_hist=None, prec=DG_FP64, ws=None, stream=None):
+        """nsteps SSP-RK3 steps with the device CFL step length (in place)."""
+        import torch
+
+        dt_dev = torch.empty(1, dtype=torch.float64, device=self.device) if dt_dev is None else dt_dev
+        ws = self.workspace("step") if ws is None else ws
+        _check(self._lib.dg_advance(self._h, _ptr(C), int(nsteps), float(cfl), _ptr(dt_dev),
+                                    _ptr(dt_hist) if dt_hist is not None else None, prec, _ptr(ws), _stream(stream)))
+        return dt_dev
 
     def rhs_vjp(self, C, Rbar, out=None, stream=None):
         out = self.empty_state() if out is None else out

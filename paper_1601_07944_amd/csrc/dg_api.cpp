@@ -19,7 +19,7 @@ struct dg_mesh_s {
     dgh::TableLayout lay;
     int64_t ws_rhs = 0, ws_step = 0, ws_vjp = 0;
     // workspace offsets (bytes)
-    size_t off_T0 = 0, off_T1 = 0, off_S = 0, off_part = 0, off_u1 = 0, off_u2 = 0;
+    size_t off_T0 = 0, off_T1 = 0, off_S = 0, off_part = 0, off_u1 = 0, off_u2 = 0, off_part4 = 0;
     size_t state_bytes = 0;
     std::vector<void*> allocs;
     // per-launch event timing (dg_timing_*)
@@ -284,7 +284,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.npad = npad;
     d.nedge = nedge;
     d.gamma = gamma;
-    d.lanes4 = N <= DG_LANES4_MAX_ELEMENTS;
+    d.lanes4 = N <= DG_LANES4_MAX_ELEMENTS || p >= 4;
     d.tab = (const double*)d_tab;
     d.tab32 = (const float*)d_tab32;
     d.geo = (const double*)d_geo;
@@ -309,7 +309,9 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     m->off_T1 = 2 * trace + part;
     m->off_u1 = 3 * trace + part;
     m->off_u2 = 3 * trace + part + state;
-    m->ws_step = (int64_t)(3 * trace + part + 2 * state);
+    m->off_part4 = 3 * trace + part + 2 * state;
+    const size_t part4 = align256((size_t)dgk::stage4_partials(d) * 8);
+    m->ws_step = (int64_t)(3 * trace + part + 2 * state + part4);
     m->state_bytes = state;
     m->ws_vjp = (int64_t)(4 * state);
     *out = m;
@@ -493,6 +495,62 @@ int dg_rhs_vjp(dg_mesh m, const double* C, const double* Rb, double* Cb, void* w
     return check_launch("dg_rhs_vjp");
 }
 
+int dg_advance(dg_mesh m, double* C, int64_t nsteps, double cfl, double* dt_dev, double* dt_hist,
+               dg_precision prec, void* ws, void* stream)
+{
+    if (!m || !C || !dt_dev || !ws) return fail(DG_EINVAL, "null argument");
+    if (nsteps < 0) return fail(DG_EINVAL, "nsteps < 0");
+    if (prec != DG_FP64 && prec != DG_MIXED) return fail(DG_EINVAL, "unknown precision %d", prec);
+    if (prec == DG_MIXED && m->surface != DG_SURFACE_ELEMENTWISE)
+        return fail(DG_EUNSUPPORTED, "DG_MIXED needs the element-wise surface mode");
+    hipStream_t s = (hipStream_t)stream;
+    const dgk::MeshDev& d = m->dev;
+    char* w = (char*)ws;
+    double* part = (double*)(w + m->off_part);
+    double* part4 = (double*)(w + m->off_part4);
+    if (m->surface != DG_SURFACE_ELEMENTWISE || !d.lanes4) {
+        // separate reduction each step
+        for (int64_t k = 0; k < nsteps; ++k) {
+            timed(m, DG_KERNEL_DT, s, [&] {
+                dgk::launch_dt(d, C, cfl, part, dt_dev, s);
+                if (dt_hist) (void)hipMemcpyAsync(dt_hist + k, dt_dev, 8, hipMemcpyDeviceToDevice, s);
+            });
+            int rc = dg_rk_step(m, C, 0.0, dt_dev, prec, ws, stream);
+            if (rc != DG_OK) return rc;
+        }
+        return check_launch("dg_advance");
+    }
+    // fused: stage 3 leaves per-block minima, stage 1 of the next step turns
+    // them into its step length (a separate final pass when they are many)
+    const bool mx = prec == DG_MIXED;
+    double* u1 = (double*)(w + m->off_u1);
+    double* u2 = (double*)(w + m->off_u2);
+    const int cnt4 = dgk::stage4_partials(d);
+    constexpr int FUSE_MAX = 4096;
+    if (nsteps > 0) timed(m, DG_KERNEL_DT, s, [&] { dgk::launch_dt_partials_only(d, C, part, s); });
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const double* pin = k == 0 ? part : part4;
+        const int cnt = k == 0 ? dgk::dt_partials(d) : cnt4;
+        dgk::FusedDt f1;
+        if (cnt <= FUSE_MAX) {
+            f1.pin = pin;
+            f1.pin_count = cnt;
+            f1.cfl = cfl;
+            f1.dt_store = dt_dev;
+            f1.dt_hist = dt_hist ? dt_hist + k : nullptr;
+        } else {
+            timed(m, DG_KERNEL_DT, s,
+                  [&] { dgk::launch_dt_final(pin, cnt, cfl, dt_dev, dt_hist ? dt_hist + k : nullptr, s); });
+        }
+        dgk::FusedDt f3;
+        f3.pout = part4;
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, 0.0, dt_dev, s, f1); });
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, mx, u1, C, u2, 0.0, dt_dev, s); });
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, mx, u2, nullptr, C, 0.0, dt_dev, s, f3); });
+    }
+    return check_launch("dg_advance");
+}
+
 int dg_rk_step_stages(dg_mesh m, double* C, double dt, const double* dt_dev, double* u1, double* u2, void* ws,
                       void* stream)
 {
@@ -549,7 +607,7 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes)
 {
     if (!m) return fail(DG_EINVAL, "null mesh");
     if (lanes != 0 && lanes != 1 && lanes != 4) return fail(DG_EINVAL, "lanes per element must be 0, 1 or 4");
-    m->dev.lanes4 = lanes == 4 || (lanes == 0 && m->dev.n <= DG_LANES4_MAX_ELEMENTS);
+    m->dev.lanes4 = lanes == 4 || (lanes == 0 && (m->dev.n <= DG_LANES4_MAX_ELEMENTS || m->dev.p >= 4));
     return ok();
 }
 

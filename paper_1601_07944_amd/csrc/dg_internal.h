@@ -52,6 +52,19 @@ struct MeshDev {
     const double* side_g = nullptr;   // [blk][9][64] outward unit normal x, y and half length per side
 };
 
+// Fused step-length bookkeeping of the multi-step path (4-lane kernels):
+// stage 1 reduces pin[0..pin_count) into its step length and stores it to
+// dt_store (and dt_hist); stage 3 writes per-block minima of the new state
+// to pout.
+struct FusedDt {
+    const double* pin = nullptr;
+    int pin_count = 0;
+    double cfl = 0.0;
+    double* dt_store = nullptr;
+    double* dt_hist = nullptr;
+    double* pout = nullptr;
+};
+
 // Launchers (dg_kernels.hip).  All asynchronous on `s`.
 void launch_traces(const MeshDev& m, const double* C, double* T, hipStream_t s);
 void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s);
@@ -63,7 +76,14 @@ void launch_element(const MeshDev& m, int mode, const double* C, const double* U
 // mode as for launch_element, except that mode 3 updates `out` in place
 // (it is the stage-0 state) and U0 must be nullptr
 void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out, double dt,
-                  const double* dt_dev, hipStream_t s);
+                  const double* dt_dev, hipStream_t s, const FusedDt& fz = FusedDt());
+// number of per-block minima a 4-lane stage 3 writes (one per 64 elements)
+inline int stage4_partials(const MeshDev& m) { return m.npad / 64; }
+// final pass of the step-length reduction over `count` minima (also writes
+// dt_hist[0] when dt_hist is not null)
+void launch_dt_final(const double* partial, int count, double cfl, double* dt_dev, double* dt_hist, hipStream_t s);
+// first pass only (dt_partials(m) minima of 256 elements each)
+void launch_dt_partials_only(const MeshDev& m, const double* C, double* partial, hipStream_t s);
 // adjoint of the fused right-hand side / RK stages (modes of k_stage_vjp)
 void launch_stage_vjp(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X, const double* Y,
                       double* out, double dt, const double* dt_dev, hipStream_t s);

@@ -275,6 +275,47 @@ __global__ __launch_bounds__(BLOCK) void k_element(int n, int npad, const double
     }
 }
 
+// ---------------------------------------------------------------- CFL step per element
+// r_in / (|v| + c) at the element mean sqrt(2) c_0; -1 for a non-physical
+// (or NaN) mean.  Shared by the reduction kernel and the fused stages, with
+// contraction off so that both evaluate it bit for bit the same way.
+__device__ __forceinline__ double dt_local(double gamma, double rin, double c0r, double c0x, double c0y, double c0e)
+{
+#pragma clang fp contract(off)
+    const double s2 = 1.4142135623730951;
+    const double rho = s2 * c0r, mx = s2 * c0x, my = s2 * c0y, E = s2 * c0e;
+    const double u = mx / rho, v = my / rho;
+    const double p = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+    if (rho > 0.0 && p > 0.0) return rin / (sqrt(u * u + v * v) + sqrt(gamma * p / rho));
+    return -1.0;
+}
+
+// min over a block of 256 values (every thread of the block must call it)
+__device__ __forceinline__ double block_min(double v, double* red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Step length for the fused multi-step path: cfl * min of the per-block
+// minima of the previous stage 3 (or of the reduction kernel), NaN if any
+// mean is non-physical.  Every block computes the same value.
+__device__ __forceinline__ double dt_from_partials(const double* __restrict__ pin, int count, double cfl, double* red)
+{
+    double v = INFINITY;
+    for (int i = threadIdx.x; i < count; i += BLOCK) v = fmin(v, pin[i]);
+    const double mn = block_min(v, red);
+    return mn < 0.0 ? __builtin_nan("") : cfl * mn;
+}
+
 // ---------------------------------------------------------------- fused stage
 // Element-wise surface integration: each work-item evaluates the numerical
 // flux of its own three sides (so every edge flux is computed twice, once
@@ -480,27 +521,48 @@ __device__ __forceinline__ float quad_bcast(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false));
 }
 
+// Fused step length (multi-step path): MODE 1 with pin != nullptr computes
+// the step length itself from the previous per-block minima pin[0..pin_count)
+// and logical block 0 stores it to dt_store (and dt_hist); MODE 3 with
+// pout != nullptr writes the minimum over its 64 elements of the new
+// state's r_in / (|v| + c) to pout[logical block].
 template <int P, int MODE, typename T>
 __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double* __restrict__ C,
                                                   const double* __restrict__ U0, double* __restrict__ out,
                                                   const double* __restrict__ geo, const int* __restrict__ snb,
                                                   const int* __restrict__ sside, const double* __restrict__ sgeo,
                                                   const T* __restrict__ tab, const double* __restrict__ tab64,
-                                                  double gamma, double dt, const double* __restrict__ dt_dev)
+                                                  double gamma, double dt, const double* __restrict__ dt_dev,
+                                                  const double* __restrict__ pin, int pin_count, double cfl,
+                                                  double* __restrict__ dt_store, double* __restrict__ dt_hist,
+                                                  double* __restrict__ pout)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
     constexpr int SS = (NE * NP) | 1;
     constexpr bool F64 = sizeof(T) == sizeof(double);
     __shared__ T phs[3 * SS];
+    __shared__ double red[BLOCK];
     for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) phs[(i / (NE * NP)) * SS + i % (NE * NP)] = tab[O::PHS + i];
     __syncthreads();
 
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    double hfused = 0.0;
+    if constexpr (MODE == 1) {
+        if (pin) {
+            hfused = dt_from_partials(pin, pin_count, cfl, red);
+            if (lb == 0 && threadIdx.x == 0) {
+                dt_store[0] = hfused;
+                if (dt_hist) dt_hist[0] = hfused;
+            }
+        }
+    }
+
     // 64 elements per workgroup; every lane stays active until the stores
     // (the quad exchanges read the neighbouring lanes)
-    const int e = xcd_block(blockIdx.x, gridDim.x) * (BLOCK / 4) + (threadIdx.x >> 2);
+    const int e = lb * (BLOCK / 4) + (threadIdx.x >> 2);
     const int m = threadIdx.x & 3;
-    if (e >= npad) return;  // whole quads (and whole workgroups) leave together
+    if (e >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
     const bool real = e < n;
     const int so = state_off(e, 4 * NP) + m * NP * LANES;
     const T s1 = T(m == 1), s2 = T(m == 2), s3 = T(m == 3);
@@ -516,6 +578,17 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
         acc[j] = T(0);
     }
     double acc0 = 0.0;
+
+    // neighbour coefficients of this lane's variable are requested one side
+    // ahead: side 0 before the volume integral, side q+1 while side q is
+    // computed, so the gathers' latency overlaps arithmetic
+    const int sides = sside[state_off(e, 1)];
+    T cn[NP];
+    {
+        const int nbo = state_off(snb[state_off(e, 3)], 4 * NP) + m * NP * LANES;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) cn[j] = T(C[nbo + j * LANES]);
+    }
 
     // volume integral, eq. (volume)
 #pragma unroll 1
@@ -538,18 +611,18 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     }
 
     // surface integral, eq. (surface)
-    const int sides = sside[state_off(e, 1)];
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
-        const int nb = snb[state_off(e, 3) + q * LANES];
+        T cx[NP];
+        if (q < 2) {
+            const int nbo = state_off(snb[state_off(e, 3) + (q + 1) * LANES], 4 * NP) + m * NP * LANES;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cx[j] = T(C[nbo + j * LANES]);
+        }
         const int qn = (sides >> (2 * q)) & 3;
         const int go = state_off(e, 9) + 3 * q * LANES;
         const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
         const double hl = sgeo[go + 2 * LANES];
-        const int nbo = state_off(nb, 4 * NP) + m * NP * LANES;
-        T cn[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) cn[j] = T(C[nbo + j * LANES]);
         const T* tq = phs + qn * SS;
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
@@ -582,29 +655,48 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
 #pragma unroll
             for (int j = 1; j < NP; ++j) acc[j] = fma(tl[j], wf, acc[j]);
         }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) cn[j] = cx[j];
     }
 
+    double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
+    if constexpr (MODE == 1) {
+        if (pin) h = hfused;
+    }
+    double mean = 0.0;  // new value of mode 0 of this lane's variable
     if (!real) {
 #pragma unroll
         for (int j = 0; j < NP; ++j) out[so + j * LANES] = 0.0;
-        return;
-    }
-    const double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
+    } else {
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const int x = so + j * LANES;
-        const double L = idet * (j == 0 ? acc0 : double(acc[j]));
-        if constexpr (MODE == 0) {
-            out[x] = L;
-        } else {
-            const double cs = F64 ? double(c[j]) : C[x];
-            if constexpr (MODE == 1) {
-                out[x] = cs + h * L;
-            } else if constexpr (MODE == 2) {
-                out[x] = 0.75 * U0[x] + 0.25 * (cs + h * L);
+        for (int j = 0; j < NP; ++j) {
+            const int x = so + j * LANES;
+            const double L = idet * (j == 0 ? acc0 : double(acc[j]));
+            double v;
+            if constexpr (MODE == 0) {
+                v = L;
             } else {
-                out[x] = (1.0 / 3.0) * out[x] + (2.0 / 3.0) * (cs + h * L);
+                const double cs = F64 ? double(c[j]) : C[x];
+                if constexpr (MODE == 1) {
+                    v = cs + h * L;
+                } else if constexpr (MODE == 2) {
+                    v = 0.75 * U0[x] + 0.25 * (cs + h * L);
+                } else {
+                    v = (1.0 / 3.0) * out[x] + (2.0 / 3.0) * (cs + h * L);
+                }
             }
+            out[x] = v;
+            if (j == 0) mean = v;
+        }
+    }
+    if constexpr (MODE == 3) {
+        if (pout) {
+            const double r0 = quad_bcast<0>(mean), r1 = quad_bcast<1>(mean), r2 = quad_bcast<2>(mean),
+                         r3 = quad_bcast<3>(mean);
+            double val = INFINITY;
+            if (real && m == 0) val = dt_local(gamma, geo[state_off(e, 6) + 5 * LANES], r0, r1, r2, r3);
+            const double mn = block_min(val, red);
+            if (threadIdx.x == 0) pout[lb] = mn;
         }
     }
 }
@@ -867,26 +959,11 @@ __global__ __launch_bounds__(BLOCK) void k_dt_partial(int n, const double* __res
     double val = INFINITY;
     if (e < n) {
         const int so = state_off(e, 4 * O::NP);
-        const double s2 = 1.4142135623730951;
-        const double rho = s2 * C[so], mx = s2 * C[so + O::NP * LANES], my = s2 * C[so + 2 * O::NP * LANES],
-                     E = s2 * C[so + 3 * O::NP * LANES];
-        const double u = mx / rho, v = my / rho;
-        const double p = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
-        const double rin = geo[state_off(e, 6) + 5 * LANES];
-        if (rho > 0.0 && p > 0.0) {
-            val = rin / (sqrt(u * u + v * v) + sqrt(gamma * p / rho));
-        } else {
-            val = -1.0;  // non-physical (also catches NaN)
-        }
+        val = dt_local(gamma, geo[state_off(e, 6) + 5 * LANES], C[so], C[so + O::NP * LANES], C[so + 2 * O::NP * LANES],
+                       C[so + 3 * O::NP * LANES]);
     }
-    red[threadIdx.x] = val;
-    __syncthreads();
-#pragma unroll
-    for (int w = BLOCK / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    const double mn = block_min(val, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = mn;
 }
 
 // L2 projection of point values (user order [N][NQ][4]) onto the
@@ -964,7 +1041,7 @@ struct Launch {
 #undef DG_ELEM
     }
     static void stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out,
-                      double dt, const double* dt_dev, hipStream_t s)
+                      double dt, const double* dt_dev, hipStream_t s, const FusedDt& fz = FusedDt())
     {
         const int nb = (m.npad + BLOCK - 1) / BLOCK;
         dim3 g((nb + 7) / 8 * 8);
@@ -975,7 +1052,8 @@ struct Launch {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
 #define DG_STAGE4(MODE, T, TAB)                                                                                  \
     k_stage4<P, MODE, T><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, TAB, \
-                                              m.tab, m.gamma, dt, dt_dev)
+                                              m.tab, m.gamma, dt, dt_dev, fz.pin, fz.pin_count, fz.cfl,          \
+                                              fz.dt_store, fz.dt_hist, fz.pout)
             if (mixed) {
                 switch (mode) {
                 case 0: DG_STAGE4(0, float, m.tab32); break;

@@ -5,19 +5,14 @@
 namespace dgk {
 
 __global__ __launch_bounds__(BLOCK) void k_dt_final(int nb, const double* __restrict__ partial, double cfl,
-                                                    double* __restrict__ dt)
+                                                    double* __restrict__ dt, double* __restrict__ hist)
 {
     __shared__ double red[BLOCK];
-    double v = INFINITY;
-    for (int i = threadIdx.x; i < nb; i += BLOCK) v = fmin(v, partial[i]);
-    red[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int w = BLOCK / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
+    const double h = dt_from_partials(partial, nb, cfl, red);
+    if (threadIdx.x == 0) {
+        dt[0] = h;
+        if (hist) hist[0] = h;
     }
-    if (threadIdx.x == 0) dt[0] = red[0] < 0.0 ? __builtin_nan("") : cfl * red[0];
 }
 
 // ---------------------------------------------------------------- layout
@@ -69,9 +64,9 @@ void launch_element(const MeshDev& m, int mode, const double* C, const double* U
 }
 
 void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out, double dt,
-                  const double* dt_dev, hipStream_t s)
+                  const double* dt_dev, hipStream_t s, const FusedDt& fz)
 {
-    DG_DISPATCH_P(m.p, stage(m, mode, mixed, C, U0, out, dt, dt_dev, s));
+    DG_DISPATCH_P(m.p, stage(m, mode, mixed, C, U0, out, dt, dt_dev, s, fz));
 }
 
 void launch_stage_vjp(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X, const double* Y,
@@ -92,7 +87,17 @@ int dt_partials(const MeshDev& m) { return (m.n + BLOCK - 1) / BLOCK; }
 void launch_dt(const MeshDev& m, const double* C, double cfl, double* partial, double* dt_dev, hipStream_t s)
 {
     DG_DISPATCH_P(m.p, dt_partial(m, C, partial, s));
-    k_dt_final<<<1, BLOCK, 0, s>>>(dt_partials(m), partial, cfl, dt_dev);
+    k_dt_final<<<1, BLOCK, 0, s>>>(dt_partials(m), partial, cfl, dt_dev, nullptr);
+}
+
+void launch_dt_partials_only(const MeshDev& m, const double* C, double* partial, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, dt_partial(m, C, partial, s));
+}
+
+void launch_dt_final(const double* partial, int count, double cfl, double* dt_dev, double* dt_hist, hipStream_t s)
+{
+    k_dt_final<<<1, BLOCK, 0, s>>>(count, partial, cfl, dt_dev, dt_hist);
 }
 
 void launch_pack(const MeshDev& m, const double* Cu, double* C, hipStream_t s)

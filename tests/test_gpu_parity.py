@@ -283,3 +283,37 @@ def test_full_size_p3_step_sampled():
     got = dm.unpack(Cg).cpu().numpy()
     dt, _ = orc.max_dt(C0, 0.3 / 7)
     check_close(got, orc.rk3_step(C0, dt))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_advance_equals_max_dt_plus_rk_step(lanes, prec):
+    # dg_advance (step length fused into the stage kernels on the 4-lane
+    # path) gives bit for bit the steps of dg_max_dt + dg_rk_step, and the
+    # step-length history
+    torch = torch_mod()
+    mesh = W.delaunay_mesh(1600, 13)
+    p = 3
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.density_jump)
+    dm = gpu_mesh(mesh, p, (ELEMENTWISE, lanes))
+    case(f"dg_advance lanes={lanes} prec={prec}")
+    A = dm.pack(to_dev(C0))
+    Bst = A.clone()
+    cfl = 0.3 / 7
+    hist = torch.empty(7, dtype=torch.float64, device="cuda")
+    dm.advance(A, 7, cfl, dt_hist=hist, prec=prec)
+    ref_hist = []
+    dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    for _ in range(7):
+        dm.max_dt(Bst, cfl, dt_dev=dt_dev, to_host=False)
+        ref_hist.append(dt_dev.clone())
+        dm.rk_step(Bst, dt_dev=dt_dev, prec=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(A, Bst)
+    assert torch.equal(hist, torch.cat(ref_hist))
+    if prec == 0:
+        ref = C0
+        for _ in range(7):
+            ref = orc.rk3_step(ref, orc.max_dt(ref, cfl)[0])
+        check_close(dm.unpack(A).cpu().numpy(), ref)
