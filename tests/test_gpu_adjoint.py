@@ -31,24 +31,27 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def gpu_mesh(mesh, p):
+def gpu_mesh(mesh, p, lanes=0):
     from paper_1601_07944_amd import binding as B
 
-    return B.DGMesh.from_mesh(mesh, p)
+    dm = B.DGMesh.from_mesh(mesh, p)
+    dm.set_lanes(lanes)
+    return dm
 
 
 MESHES = {"delaunay600": lambda: W.delaunay_mesh(600, 5), "square20": lambda: W.square_mesh(20, 1.0, 0.2, 6)}
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("mname", sorted(MESHES))
-def test_rhs_vjp_matches_oracle(p, mname):
+def test_rhs_vjp_matches_oracle(p, mname, lanes):
     mesh = MESHES[mname]()
     orc = O.Oracle(mesh, p)
     C = W.random_state(mesh.n_elem, orc.np, seed=p)
     Rb = np.random.default_rng(p).normal(size=C.shape)
-    dm = gpu_mesh(mesh, p)
-    case(f"dg_rhs_vjp p={p} {mname}")
+    dm = gpu_mesh(mesh, p, lanes)
+    case(f"dg_rhs_vjp p={p} {mname} lanes={lanes}")
     got = dm.unpack(dm.rhs_vjp(dm.pack(dev(C)), dm.pack(dev(Rb)))).cpu().numpy()
     ref = orc.rhs_vjp(C, Rb)
     assert rel_l2(got, ref) <= 1e-11
@@ -70,9 +73,10 @@ def test_rhs_vjp_dot_product_complex_step(p):
     assert abs(lhs - rhs) <= 1e-12 * np.abs(Rb * Jd).sum()
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("stored", [False, True])
 @pytest.mark.parametrize("p", [1, 3])
-def test_rk_step_vjp_matches_oracle(p, stored):
+def test_rk_step_vjp_matches_oracle(p, stored, lanes):
     import torch
 
     mesh = W.delaunay_mesh(700, 9)
@@ -80,8 +84,8 @@ def test_rk_step_vjp_matches_oracle(p, stored):
     C = orc.project(W.density_jump)
     dt, _ = orc.max_dt(C, 0.3 / (2 * p + 1))
     ub = np.random.default_rng(p).normal(size=C.shape)
-    dm = gpu_mesh(mesh, p)
-    case(f"dg_rk_step_vjp p={p} stored_stages={stored}")
+    dm = gpu_mesh(mesh, p, lanes)
+    case(f"dg_rk_step_vjp p={p} stored_stages={stored} lanes={lanes}")
     Cg = dm.pack(dev(C))
     ubg = dm.pack(dev(ub))
     if stored:
