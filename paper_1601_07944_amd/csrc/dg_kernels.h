@@ -51,13 +51,45 @@ constexpr int BLOCK = 256;
 
 __device__ __forceinline__ int state_off(int e, int nfield) { return (e >> 6) * nfield * LANES + (e & 63); }
 
+// Reciprocal and square root for the flux arithmetic: the hardware
+// approximations (v_rcp, v_rsq) refined by one Newton step, a few
+// instructions instead of the correctly rounded division / square-root
+// sequences (results within a few units in the last place; the two sides of
+// an edge call the same functions, so the flux stays exactly antisymmetric).
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double root(double y)
+{
+    const double r = __builtin_amdgcn_rsq(y);  // ~ 1/sqrt(y)
+    const double s = y * r;
+    const double h = 0.5 * r;
+    const double d = fma(-s, s, y);
+    const double s1 = fma(h, d, s);
+    return fma(h, fma(-s1, s1, y), s1);
+}
+__device__ __forceinline__ float root(float y)
+{
+    const float r = __builtin_amdgcn_rsqf(y);
+    const float s = y * r;
+    return fmaf(0.5f * r, fmaf(-s, s, y), s);
+}
+
 // ---------------------------------------------------------------- physics
 // Euler flux eq. (euler) at one point; p = (gamma-1)(E - rho |v|^2 / 2).
 // T is the arithmetic type (double, or float in the mixed-precision form).
 template <typename T>
 __device__ __forceinline__ void euler_flux(T gm1, const T U[4], T Fx[4], T Fy[4])
 {
-    const T ri = T(1) / U[0];
+    const T ri = recip(U[0]);
     const T u = U[1] * ri, v = U[2] * ri;
     const T p = gm1 * (U[3] - T(0.5) * (U[1] * u + U[2] * v));
     Fx[0] = U[1];
@@ -81,13 +113,13 @@ template <typename T>
 __device__ __forceinline__ void llf(T gamma, T gm1, const T UL[4], const T UR[4], T nx, T ny, T Fn[4])
 {
 #pragma clang fp contract(off)
-    const T riL = T(1) / UL[0], riR = T(1) / UR[0];
+    const T riL = recip(UL[0]), riR = recip(UR[0]);
     const T uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
     const T pL = gm1 * (UL[3] - T(0.5) * (UL[1] * uL + UL[2] * vL));
     const T pR = gm1 * (UR[3] - T(0.5) * (UR[1] * uR + UR[2] * vR));
     const T vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
-    const T lamL = fabs(vnL) + sqrt(gamma * pL * riL);
-    const T lamR = fabs(vnR) + sqrt(gamma * pR * riR);
+    const T lamL = fabs(vnL) + root(gamma * pL * riL);
+    const T lamR = fabs(vnR) + root(gamma * pR * riR);
     const T lam = fmax(lamL, lamR);
     const T fL[4] = {UL[0] * vnL, UL[1] * vnL + pL * nx, UL[2] * vnL + pL * ny, (UL[3] + pL) * vnL};
     const T fR[4] = {UR[0] * vnR, UR[1] * vnR + pR * nx, UR[2] * vnR + pR * ny, (UR[3] + pR) * vnR};
@@ -526,6 +558,22 @@ __device__ __forceinline__ float quad_bcast(float x)
 // and logical block 0 stores it to dt_store (and dt_hist); MODE 3 with
 // pout != nullptr writes the minimum over its 64 elements of the new
 // state's r_in / (|v| + c) to pout[logical block].
+// sum_j t[j] x[j] with two interleaved accumulators (shorter dependency
+// chain); both sides of an edge evaluate a shared trace with this same
+// order, so they get bitwise equal values
+template <int NP, typename T>
+__device__ __forceinline__ T dot2(const T* __restrict__ t, const T (&x)[NP])
+{
+    T a = T(0), b = T(0);
+#pragma unroll
+    for (int j = 0; j + 1 < NP; j += 2) {
+        a = fma(t[j], x[j], a);
+        b = fma(t[j + 1], x[j + 1], b);
+    }
+    if constexpr (NP % 2) a = fma(t[NP - 1], x[NP - 1], a);
+    return a + b;
+}
+
 template <int P, int MODE, typename T>
 __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double* __restrict__ C,
                                                   const double* __restrict__ U0, double* __restrict__ out,
@@ -593,11 +641,9 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     // volume integral, eq. (volume)
 #pragma unroll 1
     for (int k = 0; k < NQ; ++k) {
-        T um = T(0);
-#pragma unroll
-        for (int j = 0; j < NP; ++j) um = fma(tab[O::PHI + k * NP + j], c[j], um);
+        const T um = dot2<NP>(tab + O::PHI + k * NP, c);
         const T r0 = quad_bcast<0>(um), r1 = quad_bcast<1>(um), r2 = quad_bcast<2>(um), r3 = quad_bcast<3>(um);
-        const T ri = T(1) / r0;
+        const T ri = recip(r0);
         const T u = r1 * ri, v = r2 * ri;
         const T p = gm1 * (r3 - T(0.5) * (r1 * u + r2 * v));
         // F_x = U u + p (0, 1, 0, u), F_y = U v + p (0, 0, 1, v)
@@ -627,23 +673,19 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
             const T* tl = tab + O::PHS + (q * NE + k) * NP;
-            T ul = T(0), ur = T(0);
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                ul = fma(tl[j], c[j], ul);
-                ur = fma(tq[(NE - 1 - k) * NP + j], cn[j], ur);
-            }
+            const T ul = dot2<NP>(tl, c);
+            const T ur = dot2<NP>(tq + (NE - 1 - k) * NP, cn);
             T F;
             {
 #pragma clang fp contract(off)
                 const T L0 = quad_bcast<0>(ul), L1 = quad_bcast<1>(ul), L2 = quad_bcast<2>(ul), L3 = quad_bcast<3>(ul);
                 const T R0 = quad_bcast<0>(ur), R1 = quad_bcast<1>(ur), R2 = quad_bcast<2>(ur), R3 = quad_bcast<3>(ur);
-                const T riL = T(1) / L0, riR = T(1) / R0;
+                const T riL = recip(L0), riR = recip(R0);
                 const T uL = L1 * riL, vL = L2 * riL, uR = R1 * riR, vR = R2 * riR;
                 const T pL = gm1 * (L3 - T(0.5) * (L1 * uL + L2 * vL));
                 const T pR = gm1 * (R3 - T(0.5) * (R1 * uR + R2 * vR));
                 const T vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
-                const T lam = fmax(fabs(vnL) + sqrt(gam * pL * riL), fabs(vnR) + sqrt(gam * pR * riR));
+                const T lam = fmax(fabs(vnL) + root(gam * pL * riL), fabs(vnR) + root(gam * pR * riR));
                 // F.n = U vn + p (0, nx, ny, vn)
                 const T fl = ul * vnL + pL * (s1 * nx + s2 * ny + s3 * vnL);
                 const T fr = ur * vnR + pR * (s1 * nx + s2 * ny + s3 * vnR);
@@ -712,7 +754,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
 // The normal flux F.n is the case X = n_x Fb, Y = n_y Fb.
 __device__ __forceinline__ void flux_vjp(double gm1, const double U[4], const double X[4], const double Y[4], double Ub[4])
 {
-    const double ri = 1.0 / U[0];
+    const double ri = recip(U[0]);
     const double u = U[1] * ri, v = U[2] * ri;
     const double p = gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
     const double H = U[3] + p;
@@ -733,12 +775,12 @@ __device__ __forceinline__ void flux_vjp(double gm1, const double U[4], const do
 __device__ __forceinline__ void llf_vjp_left(double gamma, double gm1, const double UL[4], const double UR[4], double nx,
                                              double ny, const double Fb[4], double Ub[4])
 {
-    const double riL = 1.0 / UL[0], riR = 1.0 / UR[0];
+    const double riL = recip(UL[0]), riR = recip(UR[0]);
     const double uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
     const double pL = gm1 * (UL[3] - 0.5 * (UL[1] * uL + UL[2] * vL));
     const double pR = gm1 * (UR[3] - 0.5 * (UR[1] * uR + UR[2] * vR));
     const double vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
-    const double cL = sqrt(gamma * pL * riL), cR = sqrt(gamma * pR * riR);
+    const double cL = root(gamma * pL * riL), cR = root(gamma * pR * riR);
     const double lamL = fabs(vnL) + cL, lamR = fabs(vnR) + cR;
     const double lam = fmax(lamL, lamR);
     double X[4], Y[4], jump = 0.0;
@@ -961,7 +1003,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const dou
         const double U0 = quad_bcast<0>(um), U1 = quad_bcast<1>(um), U2 = quad_bcast<2>(um), U3 = quad_bcast<3>(um);
         const double X0 = quad_bcast<0>(xm), X1 = quad_bcast<1>(xm), X2 = quad_bcast<2>(xm), X3 = quad_bcast<3>(xm);
         const double Y0 = quad_bcast<0>(ym), Y1 = quad_bcast<1>(ym), Y2 = quad_bcast<2>(ym), Y3 = quad_bcast<3>(ym);
-        const double ri = 1.0 / U0;
+        const double ri = recip(U0);
         const double u = U1 * ri, v = U2 * ri;
         const double p = gm1 * (U3 - 0.5 * (U1 * u + U2 * v));
         const double H = U3 + p;
@@ -1007,12 +1049,12 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const dou
             const double L0 = quad_bcast<0>(ul), L1 = quad_bcast<1>(ul), L2 = quad_bcast<2>(ul), L3 = quad_bcast<3>(ul);
             const double R0 = quad_bcast<0>(ur), R1 = quad_bcast<1>(ur), R2 = quad_bcast<2>(ur), R3 = quad_bcast<3>(ur);
             const double F0 = quad_bcast<0>(fb), F1 = quad_bcast<1>(fb), F2 = quad_bcast<2>(fb), F3 = quad_bcast<3>(fb);
-            const double riL = 1.0 / L0, riR = 1.0 / R0;
+            const double riL = recip(L0), riR = recip(R0);
             const double uL = L1 * riL, vL = L2 * riL, uR = R1 * riR, vR = R2 * riR;
             const double pL = gm1 * (L3 - 0.5 * (L1 * uL + L2 * vL));
             const double pR = gm1 * (R3 - 0.5 * (R1 * uR + R2 * vR));
             const double vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
-            const double cL = sqrt(gamma * pL * riL), cR = sqrt(gamma * pR * riR);
+            const double cL = root(gamma * pL * riL), cR = root(gamma * pR * riR);
             const double lamL = fabs(vnL) + cL, lamR = fabs(vnR) + cR;
             const double lam = fmax(lamL, lamR);
             // 1/2 A_n(UL)^T Fb: flux_vjp with X = nx Fb / 2, Y = ny Fb / 2
