@@ -228,14 +228,17 @@ enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1 };
 int dg_set_surface_mode(dg_mesh m, int mode);
 
 /* Work-items per element in the element-wise kernels (forward right-hand
- * side and RK stages): 1, or 4 (one lane per conserved variable; the
- * variables of a point value are exchanged inside the quad of lanes).  Four
- * lanes give four times as many wavefronts and a quarter of the registers
- * per lane, at the price of recomputing a few flux scalars per lane; they
- * pay off on meshes too small to fill the GPU, and at p >= 4, where one
- * lane's registers cannot hold an element.  0 = automatic (4 lanes up to
+ * side and RK stages): 1 or 4.  With 4, lane m of a quad owns conserved
+ * variable m for the modal contractions (all lanes walk the same points, so
+ * the tables are read uniformly), and the flux at each point is evaluated
+ * once, by one lane of the quad, after a transpose of the point values
+ * through LDS; a second transpose returns the flux components for the lift.
+ * Four lanes give four times as many wavefronts and fewer registers per
+ * lane, at the price of more instructions per element: they pay off on
+ * meshes too small to fill the GPU, and at p >= 4, where one lane's
+ * registers cannot hold an element.  0 = automatic (4 lanes up to
  * DG_LANES4_MAX_ELEMENTS elements or for p >= 4, else 1).  Both give the
- * same result to rounding. */
+ * same result to rounding.  Returns DG_EINVAL for any other value. */
 #define DG_LANES4_MAX_ELEMENTS 1048576
 int dg_set_lanes_per_element(dg_mesh m, int lanes);
 

@@ -105,26 +105,28 @@ __device__ __forceinline__ void euler_flux(T gm1, const T U[4], T Fx[4], T Fy[4]
 // Local Lax-Friedrichs flux across unit normal n (from L to R):
 // Fn = (F(UL).n + F(UR).n)/2 - lambda/2 (UR - UL),
 // lambda = max(|vL.n| + cL, |vR.n| + cR).  Exchanging L and R and negating n
-// negates Fn bitwise.  Contraction into fused multiply-adds is off here: a
-// product fused into the sum F(UL).n + F(UR).n on one side of an edge but not
-// on the other would break that symmetry (and exact conservation) at the
-// level of the rounding unit, which in FP32 is 6e-8.
+// negates Fn bitwise, which keeps the scheme exactly conservative: every
+// quantity that depends on n is an odd function of it in floating point too
+// (products with n, and fused multiply-adds whose addend is itself odd in n),
+// and the two sides enter the final combination through a sum and a
+// difference, which are exactly symmetric.  Contraction is therefore spelled
+// out with fma() and the compiler's own fusing is off here: a product fused
+// into the sum F(UL).n + F(UR).n from one side but not the other would break
+// that symmetry at the level of the rounding unit.
 template <typename T>
 __device__ __forceinline__ void llf(T gamma, T gm1, const T UL[4], const T UR[4], T nx, T ny, T Fn[4])
 {
 #pragma clang fp contract(off)
     const T riL = recip(UL[0]), riR = recip(UR[0]);
     const T uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
-    const T pL = gm1 * (UL[3] - T(0.5) * (UL[1] * uL + UL[2] * vL));
-    const T pR = gm1 * (UR[3] - T(0.5) * (UR[1] * uR + UR[2] * vR));
-    const T vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
-    const T lamL = fabs(vnL) + root(gamma * pL * riL);
-    const T lamR = fabs(vnR) + root(gamma * pR * riR);
-    const T lam = fmax(lamL, lamR);
-    const T fL[4] = {UL[0] * vnL, UL[1] * vnL + pL * nx, UL[2] * vnL + pL * ny, (UL[3] + pL) * vnL};
-    const T fR[4] = {UR[0] * vnR, UR[1] * vnR + pR * nx, UR[2] * vnR + pR * ny, (UR[3] + pR) * vnR};
+    const T pL = gm1 * fma(T(-0.5), fma(UL[1], uL, UL[2] * vL), UL[3]);
+    const T pR = gm1 * fma(T(-0.5), fma(UR[1], uR, UR[2] * vR), UR[3]);
+    const T vnL = fma(uL, nx, vL * ny), vnR = fma(uR, nx, vR * ny);
+    const T lam = fmax(fabs(vnL) + root((gamma * riL) * pL), fabs(vnR) + root((gamma * riR) * pR));
+    const T fL[4] = {UL[0] * vnL, fma(pL, nx, UL[1] * vnL), fma(pL, ny, UL[2] * vnL), (UL[3] + pL) * vnL};
+    const T fR[4] = {UR[0] * vnR, fma(pR, nx, UR[1] * vnR), fma(pR, ny, UR[2] * vnR), (UR[3] + pR) * vnR};
 #pragma unroll
-    for (int m = 0; m < 4; ++m) Fn[m] = T(0.5) * (fL[m] + fR[m]) - T(0.5) * lam * (UR[m] - UL[m]);
+    for (int m = 0; m < 4; ++m) Fn[m] = T(0.5) * fma(-lam, UR[m] - UL[m], fL[m] + fR[m]);
 }
 
 // ---------------------------------------------------------------- traces
@@ -322,30 +324,36 @@ __device__ __forceinline__ double dt_local(double gamma, double rin, double c0r,
     return -1.0;
 }
 
-// min over a block of 256 values (every thread of the block must call it)
+// min over a block of 256 values (every thread of the block must call it):
+// within each wavefront by butterfly shuffles, then across the four
+// wavefronts through LDS.  min is exact and order-independent, so the result
+// does not depend on the reduction order.
 __device__ __forceinline__ double block_min(double v, double* red)
 {
-    red[threadIdx.x] = v;
-    __syncthreads();
 #pragma unroll
-    for (int w = BLOCK / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    const double r = red[0];
+    for (int o = LANES / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    if ((threadIdx.x & (LANES - 1)) == 0) red[threadIdx.x / LANES] = v;
     __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < BLOCK / LANES; ++w) r = fmin(r, red[w]);
+    __syncthreads();  // red may be reused
     return r;
 }
 
 // Step length for the fused multi-step path: cfl * min of the per-block
 // minima of the previous stage 3 (or of the reduction kernel), NaN if any
 // mean is non-physical.  Every block computes the same value.
+__device__ __forceinline__ double dt_from_min(double v, double cfl, double* red)
+{
+    const double mn = block_min(v, red);
+    return mn < 0.0 ? __builtin_nan("") : cfl * mn;
+}
 __device__ __forceinline__ double dt_from_partials(const double* __restrict__ pin, int count, double cfl, double* red)
 {
     double v = INFINITY;
     for (int i = threadIdx.x; i < count; i += BLOCK) v = fmin(v, pin[i]);
-    const double mn = block_min(v, red);
-    return mn < 0.0 ? __builtin_nan("") : cfl * mn;
+    return dt_from_min(v, cfl, red);
 }
 
 // ---------------------------------------------------------------- fused stage
@@ -527,14 +535,17 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
 
 // ---------------------------------------------------------------- fused stage, 4 lanes per element
 // The same right-hand side and stage update as k_stage, with the element's
-// work spread over a quad of lanes: lane m of the quad owns variable m
-// (its N_p coefficients, its accumulators, its gathered neighbour values).
-// All lanes of a wavefront walk the same volume point or side, so every
-// table read is uniform (scalar loads); the four variables of a point value
-// or trace are exchanged inside the quad with DPP broadcasts, and the few
-// scalars of the flux (1/rho, p, the wave speed) are recomputed by each lane.
-// Per-lane registers drop from ~250 to ~100 and a mesh yields four times as
-// many wavefronts, which is what small meshes need to fill 256 CUs.
+// work spread over a quad of lanes.  The contractions are split by variable:
+// lane m of the quad owns variable m (its N_p coefficients, accumulators and
+// gathered neighbour coefficients), and all lanes of a wavefront walk the
+// same volume point or side point, so every table read is uniform (scalar
+// loads).  The nonlinear flux is split by point: points are taken four at a
+// time, each lane evaluates its variable at the four points, a 4 x 4
+// transpose through LDS hands lane i the four variables at point i, lane i
+// evaluates the flux there once, and a second transpose returns flux
+// component m at the four points to lane m for the lift.  The transposes
+// stay inside one wavefront (the quad's lanes), so they need no workgroup
+// barrier, only ordering of the LDS accesses.
 
 // broadcast lane S of each quad to the whole quad
 template <int S>
@@ -553,16 +564,11 @@ __device__ __forceinline__ float quad_bcast(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false));
 }
 
-// Fused step length (multi-step path): MODE 1 with pin != nullptr computes
-// the step length itself from the previous per-block minima pin[0..pin_count)
-// and logical block 0 stores it to dt_store (and dt_hist); MODE 3 with
-// pout != nullptr writes the minimum over its 64 elements of the new
-// state's r_in / (|v| + c) to pout[logical block].
 // sum_j t[j] x[j] with two interleaved accumulators (shorter dependency
 // chain); both sides of an edge evaluate a shared trace with this same
 // order, so they get bitwise equal values
-template <int NP, typename T>
-__device__ __forceinline__ T dot2(const T* __restrict__ t, const T (&x)[NP])
+template <int NP, typename T, typename Ptr>
+__device__ __forceinline__ T dot2(Ptr t, const T (&x)[NP])
 {
     T a = T(0), b = T(0);
 #pragma unroll
@@ -574,6 +580,57 @@ __device__ __forceinline__ T dot2(const T* __restrict__ t, const T (&x)[NP])
     return a + b;
 }
 
+// Orders the LDS accesses of the lanes of one wavefront around an exchange:
+// accesses before it stay before, accesses after it stay after.  The
+// hardware executes one wavefront's LDS instructions in order, so this is
+// all an exchange between lanes of one wavefront needs.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same pointer, opaque to the optimiser: table rows read twice (trace
+// evaluation, then lift) are loaded again instead of being kept in scalar
+// registers across the exchange, which would exceed the scalar register file.
+__device__ __forceinline__ int reload(int off)
+{
+    asm volatile("" : "+s"(off));
+    return off;
+}
+
+// p + off for a per-lane offset into an LDS array, formed once (the
+// optimiser would otherwise recompute the full address for every constant
+// displacement instead of using the instruction's offset field)
+template <typename T>
+using lds_ptr = const __attribute__((address_space(3))) T*;
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> lds_row(const T* p, int off)
+{
+    lds_ptr<T> r = (lds_ptr<T>)(p + off);
+    asm volatile("" : "+v"(r));
+    return r;
+}
+
+// Exchange slots of one quad: entry (i, v) holds a pair of values for point
+// i of the current group and variable v, at pair slot 20 * quad + 5 * i + v.
+// In both access directions (lane m of a quad writing entries (i, m) for a
+// fixed i, or reading entries (m, v) for a fixed v) the 16 lanes of four
+// consecutive quads then hit 16 distinct slots modulo 16, i.e. all LDS
+// banks once.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+constexpr int XROW = 5;
+constexpr int XQUAD = 4 * XROW;
+
+// Fused step length (multi-step path): MODE 1 with pin != nullptr computes
+// the step length itself from the previous per-block minima pin[0..pin_count)
+// and logical block 0 stores it to dt_store (and dt_hist); MODE 3 with
+// pout != nullptr writes the minimum over its 64 elements of the new
+// state's r_in / (|v| + c) to pout[logical block].
 template <int P, int MODE, typename T>
 __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double* __restrict__ C,
                                                   const double* __restrict__ U0, double* __restrict__ out,
@@ -590,34 +647,36 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     constexpr int SS = (NE * NP) | 1;
     constexpr bool F64 = sizeof(T) == sizeof(double);
     __shared__ T phs[3 * SS];
-    __shared__ double red[BLOCK];
-    for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) phs[(i / (NE * NP)) * SS + i % (NE * NP)] = tab[O::PHS + i];
+    __shared__ double red[BLOCK / LANES];
+    __shared__ Pair<T> xq[(BLOCK / 4) * XQUAD];
+
+    // side tables in LDS with the points of each side in reverse order: row
+    // k of side q is the trace of mode j at the point that the neighbour
+    // across side q sees as its point k
+    for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) {
+        const int q = i / (NE * NP), r = i % (NE * NP), k = r / NP, j = r % NP;
+        phs[q * SS + (NE - 1 - k) * NP + j] = tab[O::PHS + i];
+    }
     __syncthreads();
 
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     double hfused = 0.0;
     if constexpr (MODE == 1) {
-        if (pin) {
-            hfused = dt_from_partials(pin, pin_count, cfl, red);
-            if (lb == 0 && threadIdx.x == 0) {
-                dt_store[0] = hfused;
-                if (dt_hist) dt_hist[0] = hfused;
-            }
-        }
+        if (pin) hfused = dt_from_partials(pin, pin_count, cfl, red);
     }
 
     // 64 elements per workgroup; every lane stays active until the stores
-    // (the quad exchanges read the neighbouring lanes)
+    // (the exchanges read the neighbouring lanes)
     const int e = lb * (BLOCK / 4) + (threadIdx.x >> 2);
     const int m = threadIdx.x & 3;
     if (e >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
     const bool real = e < n;
     const int so = state_off(e, 4 * NP) + m * NP * LANES;
-    const T s1 = T(m == 1), s2 = T(m == 2), s3 = T(m == 3);
     const T gam = T(gamma), gm1 = T(gamma - 1.0);
     const double* g = geo + state_off(e, 6);
     const T a00 = T(g[0]), a01 = T(g[LANES]), a10 = T(g[2 * LANES]), a11 = T(g[3 * LANES]);
     const double idet = g[4 * LANES];
+    Pair<T>* const xr = xq + (threadIdx.x >> 2) * XQUAD;
 
     T c[NP], acc[NP];
 #pragma unroll
@@ -627,83 +686,115 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     }
     double acc0 = 0.0;
 
-    // neighbour coefficients of this lane's variable are requested one side
-    // ahead: side 0 before the volume integral, side q+1 while side q is
-    // computed, so the gathers' latency overlaps arithmetic
+    // the neighbours' coefficients of this lane's variable, two sides in
+    // flight: sides 0 and 1 before the volume integral, side 2 once side 0
+    // is done, so the gathers' latency overlaps arithmetic
+    constexpr int PF = 2;
     const int sides = sside[state_off(e, 1)];
-    T cn[NP];
-    {
-        const int nbo = state_off(snb[state_off(e, 3)], 4 * NP) + m * NP * LANES;
+    const int* const nb = snb + state_off(e, 3);
+    T cn[PF][NP];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) cn[j] = T(C[nbo + j * LANES]);
+    for (int r = 0; r < PF; ++r) {
+        const int o = state_off(nb[r * LANES], 4 * NP) + m * NP * LANES;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) cn[r][j] = T(C[o + j * LANES]);
     }
 
-    // volume integral, eq. (volume)
+    // volume integral, eq. (volume), four points at a time; the last group
+    // repeats point NQ-1 where NQ is not a multiple of 4 (the repeats are
+    // evaluated and dropped)
 #pragma unroll 1
-    for (int k = 0; k < NQ; ++k) {
-        const T um = dot2<NP>(tab + O::PHI + k * NP, c);
-        const T r0 = quad_bcast<0>(um), r1 = quad_bcast<1>(um), r2 = quad_bcast<2>(um), r3 = quad_bcast<3>(um);
-        const T ri = recip(r0);
-        const T u = r1 * ri, v = r2 * ri;
-        const T p = gm1 * (r3 - T(0.5) * (r1 * u + r2 * v));
-        // F_x = U u + p (0, 1, 0, u), F_y = U v + p (0, 0, 1, v)
-        const T Fx = um * u + p * (s1 + s3 * u);
-        const T Fy = um * v + p * (s2 + s3 * v);
-        const T gr = a00 * Fx + a01 * Fy;
-        const T gs = a10 * Fx + a11 * Fy;
+    for (int k0 = 0; k0 < NQ; k0 += 4) {
 #pragma unroll
-        for (int j = 1; j < NP; ++j)
-            acc[j] = fma(tab[O::DRW + k * NP + j], gr, fma(tab[O::DSW + k * NP + j], gs, acc[j]));
+        for (int i = 0; i < 4; ++i) xr[i * XROW + m].a = dot2<NP>(tab + O::PHI + min(k0 + i, NQ - 1) * NP, c);
+        wave_sync();
+        T U[4], Fx[4], Fy[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) U[v] = xr[m * XROW + v].a;
+        euler_flux<T>(gm1, U, Fx, Fy);
+        wave_sync();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xr[m * XROW + v] = Pair<T>{a00 * Fx[v] + a01 * Fy[v], a10 * Fx[v] + a11 * Fy[v]};
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = k0 + i;
+            if (k < NQ) {
+                const Pair<T> G = xr[i * XROW + m];
+#pragma unroll
+                for (int j = 1; j < NP; ++j)
+                    acc[j] = fma(tab[O::DRW + k * NP + j], G.a, fma(tab[O::DSW + k * NP + j], G.b, acc[j]));
+            }
+        }
+        wave_sync();
     }
 
-    // surface integral, eq. (surface)
+    // surface integral, eq. (surface): per side, its p+1 Gauss points four
+    // at a time (repeating point p where p+1 is not a multiple of 4)
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
-        T cx[NP];
-        if (q < 2) {
-            const int nbo = state_off(snb[state_off(e, 3) + (q + 1) * LANES], 4 * NP) + m * NP * LANES;
-#pragma unroll
-            for (int j = 0; j < NP; ++j) cx[j] = T(C[nbo + j * LANES]);
-        }
         const int qn = (sides >> (2 * q)) & 3;
         const int go = state_off(e, 9) + 3 * q * LANES;
         const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
         const double hl = sgeo[go + 2 * LANES];
-        const T* tq = phs + qn * SS;
+        const lds_ptr<T> tq = lds_row(phs, qn * SS);
+#pragma unroll 1
+        for (int k0 = 0; k0 < NE; k0 += 4) {
 #pragma unroll
-        for (int k = 0; k < NE; ++k) {
-            const T* tl = tab + O::PHS + (q * NE + k) * NP;
-            const T ul = dot2<NP>(tl, c);
-            const T ur = dot2<NP>(tq + (NE - 1 - k) * NP, cn);
-            T F;
-            {
-#pragma clang fp contract(off)
-                const T L0 = quad_bcast<0>(ul), L1 = quad_bcast<1>(ul), L2 = quad_bcast<2>(ul), L3 = quad_bcast<3>(ul);
-                const T R0 = quad_bcast<0>(ur), R1 = quad_bcast<1>(ur), R2 = quad_bcast<2>(ur), R3 = quad_bcast<3>(ur);
-                const T riL = recip(L0), riR = recip(R0);
-                const T uL = L1 * riL, vL = L2 * riL, uR = R1 * riR, vR = R2 * riR;
-                const T pL = gm1 * (L3 - T(0.5) * (L1 * uL + L2 * vL));
-                const T pR = gm1 * (R3 - T(0.5) * (R1 * uR + R2 * vR));
-                const T vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
-                const T lam = fmax(fabs(vnL) + root(gam * pL * riL), fabs(vnR) + root(gam * pR * riR));
-                // F.n = U vn + p (0, nx, ny, vn)
-                const T fl = ul * vnL + pL * (s1 * nx + s2 * ny + s3 * vnL);
-                const T fr = ur * vnR + pR * (s1 * nx + s2 * ny + s3 * vnR);
-                F = T(0.5) * (fl + fr) - T(0.5) * lam * (ur - ul);
+            for (int i = 0; i < 4; ++i) {
+                const int k = min(k0 + i, NE - 1);
+                xr[i * XROW + m] = Pair<T>{dot2<NP>(tab + O::PHS + (q * NE + k) * NP, c), dot2<NP>(tq + k * NP, cn[0])};
             }
-            const double w = -hl * tab64[O::GW + k];
-            acc0 = fma(w * tab64[O::PHS + (q * NE + k) * NP], double(F), acc0);
-            const T wf = T(w) * F;
+            wave_sync();
+            T UL[4], UR[4], F[4];
 #pragma unroll
-            for (int j = 1; j < NP; ++j) acc[j] = fma(tl[j], wf, acc[j]);
+            for (int v = 0; v < 4; ++v) {
+                const Pair<T> t = xr[m * XROW + v];
+                UL[v] = t.a;
+                UR[v] = t.b;
+            }
+            llf<T>(gam, gm1, UL, UR, nx, ny, F);
+            wave_sync();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xr[m * XROW + v].a = F[v];
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k0 + i;
+                if (k < NE) {
+                    const T Fk = xr[i * XROW + m].a;
+                    const double w = -hl * tab64[O::GW + k];
+                    acc0 = fma(w * tab64[O::PHS + (q * NE + k) * NP], double(Fk), acc0);
+                    const T wf = T(w) * Fk;
+                    const T* tl = tab + reload(O::PHS + (q * NE + k) * NP);
+#pragma unroll
+                    for (int j = 1; j < NP; ++j) acc[j] = fma(tl[j], wf, acc[j]);
+                }
+            }
+            wave_sync();
         }
+        // the next side's neighbour moves to the front (a rolled loop
+        // cannot index registers by q)
 #pragma unroll
-        for (int j = 0; j < NP; ++j) cn[j] = cx[j];
+        for (int r = 0; r + 1 < PF; ++r)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cn[r][j] = cn[r + 1][j];
+        if (q + PF < 3) {
+            const int nbo = state_off(nb[(q + PF) * LANES], 4 * NP) + m * NP * LANES;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cn[PF - 1][j] = T(C[nbo + j * LANES]);
+        }
     }
 
     double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
     if constexpr (MODE == 1) {
-        if (pin) h = hfused;
+        if (pin) {
+            h = hfused;
+            if (lb == 0 && threadIdx.x == 0) {
+                dt_store[0] = h;
+                if (dt_hist) dt_hist[0] = h;
+            }
+        }
     }
     double mean = 0.0;  // new value of mode 0 of this lane's variable
     if (!real) {
