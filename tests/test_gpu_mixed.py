@@ -7,7 +7,7 @@ all coefficients, user layout):
     is a small difference of the volume and surface integrals, so the FP32
     rounding of the traces and fluxes (unit 6e-8, summed over O(100) terms per
     coefficient) shows up amplified; measured 0.8e-5 to 1.4e-5 for p = 1..5;
-  * state after 100 SSP-RK3 steps: <= 1e-5 (north-star bound);
+  * state after 100 SSP-RK3 steps: <= 1e-5 (the stated target for the mixed form);
   * element means stay conservative to FP64 rounding (1e-13 of the sum of
     |terms|), because both sides of an edge use bitwise equal FP32 fluxes.
 """
