@@ -33,6 +33,10 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Wall",
+    # fused multiply-adds only within one source expression (or written as
+    # fma()): the same expression then rounds the same way in every kernel
+    # that inlines it, which the bitwise-equality guarantees rely on
+    "-ffp-contract=on",
     # packed FP32 instructions stay off: plain scalar/float2 code only
     "-Xclang",
     "-target-feature",

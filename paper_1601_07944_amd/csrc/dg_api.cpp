@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -520,11 +521,11 @@ int dg_advance(dg_mesh m, double* C, int64_t nsteps, double cfl, double* dt_dev,
         }
         return check_launch("dg_advance");
     }
-    // fused: stage 3 leaves per-block minima, stage 1 of the next step turns
-    // them into its step length (a separate final pass when they are many)
     const bool mx = prec == DG_MIXED;
     double* u1 = (double*)(w + m->off_u1);
     double* u2 = (double*)(w + m->off_u2);
+    // fused: stage 3 leaves per-block minima, stage 1 of the next step turns
+    // them into its step length (a separate final pass when they are many)
     const int cnt4 = dgk::stage4_partials(d);
     constexpr int FUSE_MAX = 4096;
     if (nsteps > 0) timed(m, DG_KERNEL_DT, s, [&] { dgk::launch_dt_partials_only(d, C, part, s); });

@@ -626,65 +626,55 @@ struct alignas(2 * sizeof(T)) Pair {
 constexpr int XROW = 5;
 constexpr int XQUAD = 4 * XROW;
 
-// Fused step length (multi-step path): MODE 1 with pin != nullptr computes
-// the step length itself from the previous per-block minima pin[0..pin_count)
-// and logical block 0 stores it to dt_store (and dt_hist); MODE 3 with
-// pout != nullptr writes the minimum over its 64 elements of the new
-// state's r_in / (|v| + c) to pout[logical block].
-template <int P, int MODE, typename T>
-__global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double* __restrict__ C,
-                                                  const double* __restrict__ U0, double* __restrict__ out,
-                                                  const double* __restrict__ geo, const int* __restrict__ snb,
-                                                  const int* __restrict__ sside, const double* __restrict__ sgeo,
-                                                  const T* __restrict__ tab, const double* __restrict__ tab64,
-                                                  double gamma, double dt, const double* __restrict__ dt_dev,
-                                                  const double* __restrict__ pin, int pin_count, double cfl,
-                                                  double* __restrict__ dt_store, double* __restrict__ dt_hist,
-                                                  double* __restrict__ pout)
+// Per-lane context of the four-lane kernels: element e, variable m, the
+// element's geometry, and its quad's exchange slots.
+template <int P, typename T>
+struct Quad4 {
+    int e, m;
+    T gam, gm1, a00, a01, a10, a11;
+    double idet;
+    Pair<T>* xr;
+};
+
+template <int P, typename T>
+__device__ __forceinline__ Quad4<P, T> quad4_setup(int e, int m, double gamma, const double* __restrict__ geo,
+                                                 Pair<T>* xq)
+{
+    Quad4<P, T> z;
+    z.e = e;
+    z.m = m;
+    z.gam = T(gamma);
+    z.gm1 = T(gamma - 1.0);
+    const double* g = geo + state_off(e, 6);
+    z.a00 = T(g[0]);
+    z.a01 = T(g[LANES]);
+    z.a10 = T(g[2 * LANES]);
+    z.a11 = T(g[3 * LANES]);
+    z.idet = g[4 * LANES];
+    z.xr = xq + (threadIdx.x >> 2) * XQUAD;
+    return z;
+}
+
+// The lift of lane m's variable for the element's right-hand side, eq.
+// (2ddg0) before the inverse mass matrix: volume integral, eq. (volume),
+// and surface integral, eq. (surface), with the neighbours' coefficients
+// gathered from Cn.  acc[j] (j >= 1) in T, the mean mode acc0 in FP64.
+// phs: the side tables in LDS, sides' points reversed, rows of stride SS.
+template <int P, typename T>
+__device__ __forceinline__ void rhs_quad(const Quad4<P, T>& z, const T (&c)[Ord<P>::NP], const double* Cn,
+                                         const int* __restrict__ snb, const int* __restrict__ sside,
+                                         const double* __restrict__ sgeo, const T* __restrict__ tab,
+                                         const double* __restrict__ tab64, const T* phs,
+                                         T (&acc)[Ord<P>::NP], double& acc0)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
     constexpr int SS = (NE * NP) | 1;
-    constexpr bool F64 = sizeof(T) == sizeof(double);
-    __shared__ T phs[3 * SS];
-    __shared__ double red[BLOCK / LANES];
-    __shared__ Pair<T> xq[(BLOCK / 4) * XQUAD];
-
-    // side tables in LDS with the points of each side in reverse order: row
-    // k of side q is the trace of mode j at the point that the neighbour
-    // across side q sees as its point k
-    for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) {
-        const int q = i / (NE * NP), r = i % (NE * NP), k = r / NP, j = r % NP;
-        phs[q * SS + (NE - 1 - k) * NP + j] = tab[O::PHS + i];
-    }
-    __syncthreads();
-
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
-    double hfused = 0.0;
-    if constexpr (MODE == 1) {
-        if (pin) hfused = dt_from_partials(pin, pin_count, cfl, red);
-    }
-
-    // 64 elements per workgroup; every lane stays active until the stores
-    // (the exchanges read the neighbouring lanes)
-    const int e = lb * (BLOCK / 4) + (threadIdx.x >> 2);
-    const int m = threadIdx.x & 3;
-    if (e >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
-    const bool real = e < n;
-    const int so = state_off(e, 4 * NP) + m * NP * LANES;
-    const T gam = T(gamma), gm1 = T(gamma - 1.0);
-    const double* g = geo + state_off(e, 6);
-    const T a00 = T(g[0]), a01 = T(g[LANES]), a10 = T(g[2 * LANES]), a11 = T(g[3 * LANES]);
-    const double idet = g[4 * LANES];
-    Pair<T>* const xr = xq + (threadIdx.x >> 2) * XQUAD;
-
-    T c[NP], acc[NP];
+    const int e = z.e, m = z.m;
+    Pair<T>* const xr = z.xr;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        c[j] = T(C[so + j * LANES]);
-        acc[j] = T(0);
-    }
-    double acc0 = 0.0;
+    for (int j = 0; j < NP; ++j) acc[j] = T(0);
+    acc0 = 0.0;
 
     // the neighbours' coefficients of this lane's variable, two sides in
     // flight: sides 0 and 1 before the volume integral, side 2 once side 0
@@ -697,7 +687,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     for (int r = 0; r < PF; ++r) {
         const int o = state_off(nb[r * LANES], 4 * NP) + m * NP * LANES;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) cn[r][j] = T(C[o + j * LANES]);
+        for (int j = 0; j < NP; ++j) cn[r][j] = T(Cn[o + j * LANES]);
     }
 
     // volume integral, eq. (volume), four points at a time; the last group
@@ -711,10 +701,11 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
         T U[4], Fx[4], Fy[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) U[v] = xr[m * XROW + v].a;
-        euler_flux<T>(gm1, U, Fx, Fy);
+        euler_flux<T>(z.gm1, U, Fx, Fy);
         wave_sync();
 #pragma unroll
-        for (int v = 0; v < 4; ++v) xr[m * XROW + v] = Pair<T>{a00 * Fx[v] + a01 * Fy[v], a10 * Fx[v] + a11 * Fy[v]};
+        for (int v = 0; v < 4; ++v)
+            xr[m * XROW + v] = Pair<T>{z.a00 * Fx[v] + z.a01 * Fy[v], z.a10 * Fx[v] + z.a11 * Fy[v]};
         wave_sync();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -753,7 +744,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
                 UL[v] = t.a;
                 UR[v] = t.b;
             }
-            llf<T>(gam, gm1, UL, UR, nx, ny, F);
+            llf<T>(z.gam, z.gm1, UL, UR, nx, ny, F);
             wave_sync();
 #pragma unroll
             for (int v = 0; v < 4; ++v) xr[m * XROW + v].a = F[v];
@@ -782,9 +773,71 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
         if (q + PF < 3) {
             const int nbo = state_off(nb[(q + PF) * LANES], 4 * NP) + m * NP * LANES;
 #pragma unroll
-            for (int j = 0; j < NP; ++j) cn[PF - 1][j] = T(C[nbo + j * LANES]);
+            for (int j = 0; j < NP; ++j) cn[PF - 1][j] = T(Cn[nbo + j * LANES]);
         }
     }
+}
+
+// side tables into LDS with the points of each side in reverse order: row k
+// of side q is the trace of mode j at the point that the neighbour across
+// side q sees as its point k (every thread of the block calls it)
+template <int P, typename T>
+__device__ __forceinline__ void load_side_tables(const T* __restrict__ tab, T* phs)
+{
+    using O = Ord<P>;
+    constexpr int NP = O::NP, NE = O::NE, SS = (NE * NP) | 1;
+    for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) {
+        const int q = i / (NE * NP), r = i % (NE * NP), k = r / NP, j = r % NP;
+        phs[q * SS + (NE - 1 - k) * NP + j] = tab[O::PHS + i];
+    }
+    __syncthreads();
+}
+
+// Fused step length (multi-step path): MODE 1 with pin != nullptr computes
+// the step length itself from the previous per-block minima pin[0..pin_count)
+// and logical block 0 stores it to dt_store (and dt_hist); MODE 3 with
+// pout != nullptr writes the minimum over its 64 elements of the new
+// state's r_in / (|v| + c) to pout[logical block].
+template <int P, int MODE, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double* __restrict__ C,
+                                                  const double* __restrict__ U0, double* __restrict__ out,
+                                                  const double* __restrict__ geo, const int* __restrict__ snb,
+                                                  const int* __restrict__ sside, const double* __restrict__ sgeo,
+                                                  const T* __restrict__ tab, const double* __restrict__ tab64,
+                                                  double gamma, double dt, const double* __restrict__ dt_dev,
+                                                  const double* __restrict__ pin, int pin_count, double cfl,
+                                                  double* __restrict__ dt_store, double* __restrict__ dt_hist,
+                                                  double* __restrict__ pout)
+{
+    using O = Ord<P>;
+    constexpr int NP = O::NP, NE = O::NE;
+    constexpr int SS = (NE * NP) | 1;
+    constexpr bool F64 = sizeof(T) == sizeof(double);
+    __shared__ T phs[3 * SS];
+    __shared__ double red[BLOCK / LANES];
+    __shared__ Pair<T> xq[(BLOCK / 4) * XQUAD];
+    load_side_tables<P, T>(tab, phs);
+
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    double hfused = 0.0;
+    if constexpr (MODE == 1) {
+        if (pin) hfused = dt_from_partials(pin, pin_count, cfl, red);
+    }
+
+    // 64 elements per workgroup; every lane stays active until the stores
+    // (the exchanges read the neighbouring lanes)
+    const int e = lb * (BLOCK / 4) + (threadIdx.x >> 2);
+    const int m = threadIdx.x & 3;
+    if (e >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
+    const bool real = e < n;
+    const int so = state_off(e, 4 * NP) + m * NP * LANES;
+    const Quad4<P, T> z = quad4_setup<P, T>(e, m, gamma, geo, xq);
+
+    T c[NP], acc[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) c[j] = T(C[so + j * LANES]);
+    double acc0;
+    rhs_quad<P, T>(z, c, C, snb, sside, sgeo, tab, tab64, phs, acc, acc0);
 
     double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
     if constexpr (MODE == 1) {
@@ -804,7 +857,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             const int x = so + j * LANES;
-            const double L = idet * (j == 0 ? acc0 : double(acc[j]));
+            const double L = z.idet * (j == 0 ? acc0 : double(acc[j]));
             double v;
             if constexpr (MODE == 0) {
                 v = L;
