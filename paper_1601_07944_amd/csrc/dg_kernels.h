@@ -1095,10 +1095,12 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp(int n, int npad, const doub
         }
 }
 
-// The adjoint with 4 lanes per element (lane m: variable m), as k_stage4 is
-// to k_stage: the components of point values, traces and flux cotangents are
-// exchanged inside the quad; each lane evaluates its own component of the
-// closed-form cotangents of flux_vjp and llf_vjp_left.  Modes as k_stage_vjp.
+// The adjoint with 4 lanes per element, organised as k_stage4: lane m owns
+// variable m for the contractions (state, right-hand-side cotangent and the
+// neighbours' ones), points are taken four at a time, and two transposes
+// through LDS let lane i evaluate the full closed-form cotangent (flux_vjp,
+// llf_vjp_left) at point i once and hand component m back to lane m.
+// Modes as k_stage_vjp.
 template <int P, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const double* __restrict__ C,
                                                       const double* __restrict__ Rb, const double* __restrict__ X,
@@ -1112,18 +1114,20 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const dou
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
     constexpr int SS = (NE * NP) | 1;
     __shared__ double phs[3 * SS];
-    for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) phs[(i / (NE * NP)) * SS + i % (NE * NP)] = tab[O::PHS + i];
-    __syncthreads();
+    __shared__ Pair<double> xa[(BLOCK / 4) * XQUAD];
+    __shared__ Pair<double> xb[(BLOCK / 4) * XQUAD];
+    load_side_tables<P, double>(tab, phs);
 
     const int e = xcd_block(blockIdx.x, gridDim.x) * (BLOCK / 4) + (threadIdx.x >> 2);
     const int m = threadIdx.x & 3;
     if (e >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
     const bool real = e < n;
     const int so = state_off(e, 4 * NP) + m * NP * LANES;
-    const double s0 = m == 0, s1 = m == 1, s2 = m == 2, s3 = m == 3;
     const double gm1 = gamma - 1.0;
     const double* g = geo + state_off(e, 6);
     const double a00 = g[0], a01 = g[LANES], a10 = g[2 * LANES], a11 = g[3 * LANES], idet = g[4 * LANES];
+    Pair<double>* const ra = xa + (threadIdx.x >> 2) * XQUAD;
+    Pair<double>* const rb = xb + (threadIdx.x >> 2) * XQUAD;
 
     double c[NP], rs[NP], cb[NP];
 #pragma unroll
@@ -1133,92 +1137,127 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const dou
         cb[j] = 0.0;
     }
 
-    // volume
-#pragma unroll 1
-    for (int k = 0; k < NQ; ++k) {
-        double um = 0.0, gr = 0.0, gs = 0.0;
+    // the neighbours' coefficients and right-hand-side cotangents of this
+    // lane's variable; up to p = 3 the next side's are requested while a
+    // side is computed
+    constexpr int PF = P <= 3 ? 2 : 1;
+    const int sides = sside[state_off(e, 1)];
+    const int* const nbp = snb + state_off(e, 3);
+    double cn[PF][NP], rn[PF][NP];
+#pragma unroll
+    for (int r = 0; r < PF; ++r) {
+        const int nb = nbp[r * LANES];
+        const double idn = geo[state_off(nb, 6) + 4 * LANES];
+        const int o = state_off(nb, 4 * NP) + m * NP * LANES;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            um = fma(tab[O::PHI + k * NP + j], c[j], um);
-            gr = fma(tab[O::DRW + k * NP + j], rs[j], gr);
-            gs = fma(tab[O::DSW + k * NP + j], rs[j], gs);
+            cn[r][j] = C[o + j * LANES];
+            rn[r][j] = idn * Rb[o + j * LANES];
         }
-        const double xm = a00 * gr + a10 * gs, ym = a01 * gr + a11 * gs;
-        const double U0 = quad_bcast<0>(um), U1 = quad_bcast<1>(um), U2 = quad_bcast<2>(um), U3 = quad_bcast<3>(um);
-        const double X0 = quad_bcast<0>(xm), X1 = quad_bcast<1>(xm), X2 = quad_bcast<2>(xm), X3 = quad_bcast<3>(xm);
-        const double Y0 = quad_bcast<0>(ym), Y1 = quad_bcast<1>(ym), Y2 = quad_bcast<2>(ym), Y3 = quad_bcast<3>(ym);
-        const double ri = recip(U0);
-        const double u = U1 * ri, v = U2 * ri;
-        const double p = gm1 * (U3 - 0.5 * (U1 * u + U2 * v));
-        const double H = U3 + p;
-        const double Ku = X0 * U0 + X1 * U1 + X2 * U2 + X3 * H;
-        const double Kv = Y0 * U0 + Y1 * U1 + Y2 * U2 + Y3 * H;
-        const double Pp = (X1 + Y2 + u * X3 + v * Y3) * gm1;
-        const double ub = u * xm + v * ym + s0 * (-(Ku * u + Kv * v) * ri + Pp * 0.5 * (u * u + v * v)) +
-                          s1 * (Ku * ri - Pp * u) + s2 * (Kv * ri - Pp * v) + s3 * Pp;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) cb[j] = fma(tab[O::PHI + k * NP + j], ub, cb[j]);
     }
 
-    // surface
-    const int sides = sside[state_off(e, 1)];
+    // volume: U, and the cotangents X, Y of the x and y fluxes, at four points
+#pragma unroll 1
+    for (int k0 = 0; k0 < NQ; k0 += 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = min(k0 + i, NQ - 1);
+            const double um = dot2<NP>(tab + O::PHI + k * NP, c);
+            const double gr = dot2<NP>(tab + O::DRW + k * NP, rs);
+            const double gs = dot2<NP>(tab + O::DSW + k * NP, rs);
+            ra[i * XROW + m] = Pair<double>{um, a00 * gr + a10 * gs};
+            rb[i * XROW + m].a = a01 * gr + a11 * gs;
+        }
+        wave_sync();
+        double U[4], Xv[4], Yv[4], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const Pair<double> t = ra[m * XROW + v];
+            U[v] = t.a;
+            Xv[v] = t.b;
+            Yv[v] = rb[m * XROW + v].a;
+        }
+        flux_vjp(gm1, U, Xv, Yv, Ub);
+        wave_sync();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ra[m * XROW + v].a = Ub[v];
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = k0 + i;
+            if (k < NQ) {
+                const double ub = ra[i * XROW + m].a;
+                const double* tp = tab + reload(O::PHI + k * NP);
+#pragma unroll
+                for (int j = 0; j < NP; ++j) cb[j] = fma(tp[j], ub, cb[j]);
+            }
+        }
+        wave_sync();
+    }
+
+    // surface: traces of both sides and the flux cotangent Fb at four points
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
-        const int nb = snb[state_off(e, 3) + q * LANES];
         const int qn = (sides >> (2 * q)) & 3;
         const int go = state_off(e, 9) + 3 * q * LANES;
         const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
-        const double idn = geo[state_off(nb, 6) + 4 * LANES];
-        const int nbo = state_off(nb, 4 * NP) + m * NP * LANES;
-        double cn[NP], rn[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            cn[j] = C[nbo + j * LANES];
-            rn[j] = idn * Rb[nbo + j * LANES];
-        }
-        const double* tq = phs + qn * SS;
+        const lds_ptr<double> tq = lds_row(phs, qn * SS);
 #pragma unroll 1
-        for (int k = 0; k < NE; ++k) {
-            const double* tl = tab + O::PHS + (q * NE + k) * NP;
-            double ul = 0.0, rl = 0.0, ur = 0.0, rr = 0.0;
+        for (int k0 = 0; k0 < NE; k0 += 4) {
+            // (one point at a time: the neighbour's side table comes from LDS
+            // into vector registers, four rows at once would not fit at p = 5)
+#pragma unroll 1
+            for (int i = 0; i < 4; ++i) {
+                const int k = min(k0 + i, NE - 1);
+                const double* tl = tab + O::PHS + (q * NE + k) * NP;
+                const double ul = dot2<NP>(tl, c), rl = dot2<NP>(tl, rs);
+                const double ur = dot2<NP>(tq + k * NP, cn[0]), rr = dot2<NP>(tq + k * NP, rn[0]);
+                ra[i * XROW + m] = Pair<double>{ul, ur};
+                rb[i * XROW + m].a = -hl * tab[O::GW + k] * (rl - rr);
+            }
+            wave_sync();
+            double UL[4], UR[4], Fb[4], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const Pair<double> t = ra[m * XROW + v];
+                UL[v] = t.a;
+                UR[v] = t.b;
+                Fb[v] = rb[m * XROW + v].a;
+            }
+            llf_vjp_left(gamma, gm1, UL, UR, nx, ny, Fb, Ub);
+            wave_sync();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ra[m * XROW + v].a = Ub[v];
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k0 + i;
+                if (k < NE) {
+                    const double ub = ra[i * XROW + m].a;
+                    const double* tl = tab + reload(O::PHS + (q * NE + k) * NP);
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) cb[j] = fma(tl[j], ub, cb[j]);
+                }
+            }
+            wave_sync();
+        }
+        // the next side's neighbour moves to the front
+#pragma unroll
+        for (int r = 0; r + 1 < PF; ++r)
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
-                const double t = tq[(NE - 1 - k) * NP + j];
-                ul = fma(tl[j], c[j], ul);
-                rl = fma(tl[j], rs[j], rl);
-                ur = fma(t, cn[j], ur);
-                rr = fma(t, rn[j], rr);
+                cn[r][j] = cn[r + 1][j];
+                rn[r][j] = rn[r + 1][j];
             }
-            const double fb = -hl * tab[O::GW + k] * (rl - rr);
-            const double L0 = quad_bcast<0>(ul), L1 = quad_bcast<1>(ul), L2 = quad_bcast<2>(ul), L3 = quad_bcast<3>(ul);
-            const double R0 = quad_bcast<0>(ur), R1 = quad_bcast<1>(ur), R2 = quad_bcast<2>(ur), R3 = quad_bcast<3>(ur);
-            const double F0 = quad_bcast<0>(fb), F1 = quad_bcast<1>(fb), F2 = quad_bcast<2>(fb), F3 = quad_bcast<3>(fb);
-            const double riL = recip(L0), riR = recip(R0);
-            const double uL = L1 * riL, vL = L2 * riL, uR = R1 * riR, vR = R2 * riR;
-            const double pL = gm1 * (L3 - 0.5 * (L1 * uL + L2 * vL));
-            const double pR = gm1 * (R3 - 0.5 * (R1 * uR + R2 * vR));
-            const double vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
-            const double cL = root(gamma * pL * riL), cR = root(gamma * pR * riR);
-            const double lamL = fabs(vnL) + cL, lamR = fabs(vnR) + cR;
-            const double lam = fmax(lamL, lamR);
-            // 1/2 A_n(UL)^T Fb: flux_vjp with X = nx Fb / 2, Y = ny Fb / 2
-            const double HL = L3 + pL;
-            const double KF = F0 * L0 + F1 * L1 + F2 * L2 + F3 * HL;
-            const double Ku = 0.5 * nx * KF, Kv = 0.5 * ny * KF;
-            const double Pp = 0.5 * (nx * F1 + ny * F2 + (uL * nx + vL * ny) * F3) * gm1;
-            double ub = 0.5 * vnL * fb + s0 * (-(Ku * uL + Kv * vL) * riL + Pp * 0.5 * (uL * uL + vL * vL)) +
-                        s1 * (Ku * riL - Pp * uL) + s2 * (Kv * riL - Pp * vL) + s3 * Pp;
-            ub += 0.5 * lam * fb;
-            if (lamL >= lamR) {
-                const double jump = F0 * (R0 - L0) + F1 * (R1 - L1) + F2 * (R2 - L2) + F3 * (R3 - L3);
-                const double lb = -0.5 * jump;
-                const double sv = vnL >= 0.0 ? lb : -lb;
-                const double pb = lb * cL / (2.0 * pL);
-                ub += s0 * (-sv * vnL * riL - lb * cL * riL * 0.5 + pb * gm1 * 0.5 * (uL * uL + vL * vL)) +
-                      s1 * (sv * nx * riL - pb * gm1 * uL) + s2 * (sv * ny * riL - pb * gm1 * vL) + s3 * (pb * gm1);
-            }
+        if (q + PF < 3) {
+            const int nb = nbp[(q + PF) * LANES];
+            const double idn = geo[state_off(nb, 6) + 4 * LANES];
+            const int o = state_off(nb, 4 * NP) + m * NP * LANES;
 #pragma unroll
-            for (int j = 0; j < NP; ++j) cb[j] = fma(tl[j], ub, cb[j]);
+            for (int j = 0; j < NP; ++j) {
+                cn[PF - 1][j] = C[o + j * LANES];
+                rn[PF - 1][j] = idn * Rb[o + j * LANES];
+            }
         }
     }
 
