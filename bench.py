@@ -106,9 +106,11 @@ def cpu_baseline(mesh, p, seconds: float):
 def run_scale(args):
     """Per-order throughput at scale (one JSON line with a list): periodic
     unit square, density jump across r < 0.25 about (0.5, 0.5) on the smooth
-    density wave (u = v = 0.5, p = 1), FP64 and mixed precision, K steps
-    each; the stage kernel's algorithmic bytes per launch over its mean
-    launch time against the HBM peak."""
+    density wave (u = v = 0.5, p = 1), or the smooth wave alone
+    (--data smooth), FP64 and mixed precision, K steps each; the stage
+    kernel's algorithmic bytes per launch over its mean launch time against
+    the HBM peak, and the mixed form's state difference to FP64 after the
+    K steps."""
     import numpy as np
     import torch
 
@@ -129,22 +131,28 @@ def run_scale(args):
     for p in [int(x) for x in args.orders.split(",")]:
         dm = B.DGMesh.from_mesh(mesh, p)
         xy = dm.quad_points().cpu().numpy()
-        C0 = dm.project(torch.from_numpy(np.ascontiguousarray(W.density_jump(xy[..., 0], xy[..., 1]))).to(dev))
+        init = W.smooth_density if args.data == "smooth" else W.density_jump
+        C0 = dm.project(torch.from_numpy(np.ascontiguousarray(init(xy[..., 0], xy[..., 1]))).to(dev))
         del xy
         ws = dm.workspace("step")
         dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
         cfl = 0.3 / (2 * p + 1)
         dof = dm.n * dm.np * 4
         row = {"p": p, "n_elem": dm.n, "dof": dof}
-        for name, prec, lanes in (("fp64", B.DG_FP64, 0), ("mixed", B.DG_MIXED, 0), ("fp64_lanes1", B.DG_FP64, 1),
-                                  ("fp64_lanes4", B.DG_FP64, 4)):
+        finals = {}
+        variants = [("fp64", B.DG_FP64, 0), ("mixed", B.DG_MIXED, 0)]
+        if not args.no_lane_variants:
+            variants += [("fp64_lanes1", B.DG_FP64, 1), ("fp64_lanes4", B.DG_FP64, 4)]
+        for name, prec, lanes in variants:
             dm.set_lanes(lanes)
             C = C0.clone()
 
             def step(k=1):
                 dm.advance(C, k, cfl, dt_dev=dt_dev, prec=prec, ws=ws)
 
-            step(3)
+            Cw = C0.clone()  # warm-up on a copy, so that C takes exactly K steps
+            dm.advance(Cw, 2, cfl, dt_dev=dt_dev, prec=prec, ws=ws)
+            del Cw
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
@@ -153,6 +161,8 @@ def run_scale(args):
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.steps
+            if name in ("fp64", "mixed"):
+                finals[name] = C.clone()
             dm.timing(True)
             step(min(args.steps, 10))
             torch.cuda.synchronize()
@@ -171,13 +181,18 @@ def run_scale(args):
             print(f"[scale] p={p} {name}: {row[name]}", file=sys.stderr, flush=True)
             del C
         row["mixed_speedup"] = row["fp64"]["ms_per_step"] / row["mixed"]["ms_per_step"]
+        row["mixed_rel_l2_vs_fp64"] = float(torch.linalg.norm(finals["mixed"] - finals["fp64"]) /
+                                            torch.linalg.norm(finals["fp64"]))
+        print(f"[scale] p={p} mixed speedup {row['mixed_speedup']:.3f}, state difference "
+              f"{row['mixed_rel_l2_vs_fp64']:.2e}", file=sys.stderr, flush=True)
+        del finals
         res.append(row)
         dm.close()
         del C0, ws
         torch.cuda.empty_cache()
     out = {
-        "workload": f"density jump on the smooth wave, periodic unit square, {mesh.n_elem} triangles ({args.mesh}), "
-        f"SSP-RK3 steps with device CFL step",
+        "workload": f"{'smooth density wave' if args.data == 'smooth' else 'density jump on the smooth wave'}, "
+        f"periodic unit square, {mesh.n_elem} triangles ({args.mesh}), SSP-RK3 steps with device CFL step",
         "steps": args.steps,
         "orders": res,
     }
@@ -202,6 +217,8 @@ def main():
     ap.add_argument("--mesh", choices=["square", "delaunay"], default="square", help="scale workload mesh")
     ap.add_argument("--n-tri", type=int, default=4_000_000, help="scale workload triangles")
     ap.add_argument("--orders", default="1,2,3,4,5", help="scale workload orders")
+    ap.add_argument("--data", choices=["jump", "smooth"], default="jump", help="scale workload initial data")
+    ap.add_argument("--no-lane-variants", action="store_true", help="scale workload: automatic lanes only")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(
