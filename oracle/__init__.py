@@ -66,6 +66,10 @@ def _configure(lib):
     lib.orc_max_dt.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp]
     lib.orc_max_dt.restype = ctypes.c_int
     lib.orc_rk3_step.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
+    lib.orc_limit_bj.argtypes = [ctypes.c_void_p, _dp]
+    lib.orc_limit_bj.restype = ctypes.c_int
+    lib.orc_rk3_step_limited.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
+    lib.orc_rk3_step_limited.restype = ctypes.c_int
     lib.orc_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
     _cp = ctypes.POINTER(ctypes.c_double * 2)
     lib.orc_cs_rhs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -251,9 +255,22 @@ class Oracle:
         rc = self._lib.orc_max_dt(self._ctx, _p(C), float(cfl), _p(dt))
         return float(dt[0]), rc
 
-    def rk3_step(self, C, dt):
+    def rk3_step(self, C, dt, limit=False):
+        """One SSP-RK3 step; with limit=True (p = 1 only) the Barth-Jespersen
+        limiter is applied after every stage and to the new state."""
         C = self._state(C).copy()
-        self._lib.orc_rk3_step(self._ctx, _p(C), float(dt))
+        if limit:
+            if self._lib.orc_rk3_step_limited(self._ctx, _p(C), float(dt)) != 0:
+                raise ValueError("the limiter is defined for p = 1 only")
+        else:
+            self._lib.orc_rk3_step(self._ctx, _p(C), float(dt))
+        return C
+
+    def limit(self, C):
+        """Barth-Jespersen slope limiter (p = 1): a limited copy of C."""
+        C = self._state(C).copy()
+        if self._lib.orc_limit_bj(self._ctx, _p(C)) != 0:
+            raise ValueError("the limiter is defined for p = 1 only")
         return C
 
     # -- error norms -------------------------------------------------------

@@ -22,7 +22,9 @@
  *     "Surface Integration Kernel": the two elements traverse a shared edge
  *     in opposite directions);
  *   - L2 projection onto the orthonormal basis (mass matrix = det J * I);
- *   - three-stage SSP Runge-Kutta in Shu-Osher form and a CFL time step.
+ *   - three-stage SSP Runge-Kutta in Shu-Osher form and a CFL time step;
+ *   - the Barth-Jespersen slope limiter for p = 1 (Section "Limiting
+ *     Kernel"), optionally applied after every RK stage.
  *
  * Conventions (readings of points the paper leaves open):
  *   - J = d(x,y)/d(r,s) = [[x2-x1, x3-x1], [y2-y1, y3-y1]];
@@ -368,6 +370,90 @@ void orc_rk3_step(const orc_ctx *c, double *C, double dt)
     free(L);
     free(u1);
     free(u2);
+}
+
+/* ------------------------------------------------------------- limiter */
+/* Barth-Jespersen slope limiter for p = 1 (Section "Limiting Kernel", eqs.
+ * (limit), (limitmax), (limitmin)), each conserved variable separately:
+ *   - centroid values: U_i at its own centroid (1/3, 1/3) and each
+ *     neighbour's U at its own centroid, all from the input state;
+ *   - Umax, Umin: the largest and smallest of the four;
+ *   - at every Gauss point r_qk of the element's three sides, with
+ *     d = U_i(r_qk) - U_i(centroid): alpha_k = min(1, (Umax - U_i(centroid)) / d)
+ *     if d > 0, min(1, (Umin - U_i(centroid)) / d) if d < 0, and 1 if d = 0;
+ *   - alpha = the smallest alpha_k multiplies the two linear coefficients
+ *     (modes 1 and 2); mode 0 is left as it is.
+ * Returns -1 (state untouched) unless p = 1. */
+int orc_limit_bj(const orc_ctx *c, double *C)
+{
+    if (c->p != 1) return -1;
+    const int np = c->np;
+    double phic[NP_MAX];
+    orc_basis(c->p, 1.0 / 3.0, 1.0 / 3.0, phic, NULL, NULL);
+    double *cen = (double *)malloc(sizeof(double) * c->n * M);
+    for (int64_t i = 0; i < c->n; ++i)
+        for (int m = 0; m < M; ++m) {
+            double u = 0.0;
+            for (int j = 0; j < np; ++j) u += phic[j] * C[(i * M + m) * np + j];
+            cen[i * M + m] = u;
+        }
+    double *alpha = (double *)malloc(sizeof(double) * c->n * M);
+    for (int64_t i = 0; i < c->n; ++i)
+        for (int m = 0; m < M; ++m) {
+            const double ub = cen[i * M + m];
+            double umax = ub, umin = ub;
+            for (int q = 0; q < 3; ++q) {
+                const double un = cen[c->nbr[i * 3 + q] * M + m];
+                if (un > umax) umax = un;
+                if (un < umin) umin = un;
+            }
+            double a = 1.0;
+            for (int q = 0; q < 3; ++q)
+                for (int k = 0; k < c->ne; ++k) {
+                    double u = 0.0;
+                    for (int j = 0; j < np; ++j) u += c->phi_s[(q * c->ne + k) * np + j] * C[(i * M + m) * np + j];
+                    const double d = u - ub;
+                    double ak = 1.0;
+                    if (d > 0.0)
+                        ak = (umax - ub) / d;
+                    else if (d < 0.0)
+                        ak = (umin - ub) / d;
+                    if (ak > 1.0) ak = 1.0;
+                    if (ak < a) a = ak;
+                }
+            alpha[i * M + m] = a;
+        }
+    for (int64_t i = 0; i < c->n; ++i)
+        for (int m = 0; m < M; ++m)
+            for (int j = 1; j < np; ++j) C[(i * M + m) * np + j] *= alpha[i * M + m];
+    free(cen);
+    free(alpha);
+    return 0;
+}
+
+/* orc_rk3_step with the limiter applied to each stage's result and to the
+ * new state (Section "Time-stepping": intermediate stages and the next time
+ * level are both limited). */
+int orc_rk3_step_limited(const orc_ctx *c, double *C, double dt)
+{
+    if (c->p != 1) return -1;
+    size_t len = (size_t)c->n * M * c->np;
+    double *L = (double *)malloc(sizeof(double) * len);
+    double *u1 = (double *)malloc(sizeof(double) * len);
+    double *u2 = (double *)malloc(sizeof(double) * len);
+    orc_rhs(c, C, L);
+    for (size_t x = 0; x < len; ++x) u1[x] = C[x] + dt * L[x];
+    orc_limit_bj(c, u1);
+    orc_rhs(c, u1, L);
+    for (size_t x = 0; x < len; ++x) u2[x] = 0.75 * C[x] + 0.25 * (u1[x] + dt * L[x]);
+    orc_limit_bj(c, u2);
+    orc_rhs(c, u2, L);
+    for (size_t x = 0; x < len; ++x) C[x] = (1.0 / 3.0) * C[x] + (2.0 / 3.0) * (u2[x] + dt * L[x]);
+    orc_limit_bj(c, C);
+    free(L);
+    free(u1);
+    free(u2);
+    return 0;
 }
 
 int orc_set_threads(int n)

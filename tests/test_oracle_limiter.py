@@ -1,0 +1,137 @@
+"""Pins of the oracle's Barth-Jespersen limiter (p = 1, Section "Limiting
+Kernel"), CPU only.
+
+The limiter's defining properties are checked from outside its code: side
+point values are evaluated with the oracle's basis at side points built here
+from the side convention, and the centroid bounds from the centroid values
+of each element and its three neighbours.
+  * the mean of every element and variable is untouched, and both linear
+    coefficients are scaled by one common alpha in [0, 1];
+  * no new extrema: after limiting, every side Gauss point value lies in
+    [Umin, Umax] of the centroid values;
+  * alpha is the largest such factor: where alpha < 1 some side point value
+    sits on Umin or Umax; where the unlimited values already lie within the
+    bounds, nothing changes.
+Together these fix alpha uniquely (the side values are affine in alpha).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_07944_amd import workloads as W
+
+
+def side_points(p):
+    x, _ = np.polynomial.legendre.leggauss(p + 1)
+    r, s = [], []
+    for q in range(3):
+        for xi in x:
+            if q == 0:
+                r.append(0.5 * (1 + xi)), s.append(0.0)
+            elif q == 1:
+                r.append(0.5 * (1 - xi)), s.append(0.5 * (1 + xi))
+            else:
+                r.append(0.0), s.append(0.5 * (1 - xi))
+    return np.array(r), np.array(s)
+
+
+def centroid_bounds(orc, mesh, C):
+    cen = orc.eval(C, np.array([1 / 3]), np.array([1 / 3]))[:, 0, :]  # [N, 4]
+    allc = np.concatenate([cen[:, None, :], cen[mesh.nbr_elem]], axis=1)
+    return cen, allc.max(axis=1), allc.min(axis=1)
+
+
+def rough_state(n, seed):
+    # means physical, linear modes large enough that the limiter acts often
+    rng = np.random.default_rng(seed)
+    C = W.random_state(n, 3, seed=seed)
+    C[:, :, 1:] += rng.normal(scale=0.08, size=(n, 4, 2))
+    return C
+
+
+def alphas(C, L):
+    a1 = np.where(C[:, :, 1] != 0, L[:, :, 1] / np.where(C[:, :, 1] != 0, C[:, :, 1], 1), np.nan)
+    a2 = np.where(C[:, :, 2] != 0, L[:, :, 2] / np.where(C[:, :, 2] != 0, C[:, :, 2], 1), np.nan)
+    return a1, a2
+
+
+def check_limited(orc, mesh, C, L, tol=1e-12):
+    rs = side_points(1)
+    # means untouched, one common factor in [0, 1] for both linear modes
+    assert np.array_equal(L[:, :, 0], C[:, :, 0])
+    a1, a2 = alphas(C, L)
+    both = np.isfinite(a1) & np.isfinite(a2)
+    assert np.allclose(a1[both], a2[both], rtol=1e-12, atol=1e-14)
+    a = np.where(np.isfinite(a1), a1, a2)
+    a = np.where(np.isfinite(a), a, 1.0)
+    assert np.all(a >= -1e-15) and np.all(a <= 1 + 1e-15)
+    # no new extrema at the side Gauss points
+    cen, umax, umin = centroid_bounds(orc, mesh, C)
+    scale = np.abs(C).max()
+    vals = orc.eval(L, *rs)  # [N, 6, 4]
+    assert np.all(vals <= umax[:, None, :] + tol * scale)
+    assert np.all(vals >= umin[:, None, :] - tol * scale)
+    # largest such factor
+    hit = np.minimum(np.abs(vals - umax[:, None, :]), np.abs(vals - umin[:, None, :])).min(axis=1)
+    limited = a < 1 - 1e-12
+    assert np.all(hit[limited] <= tol * scale)
+    raw = orc.eval(C, *rs)
+    inside = np.all((raw <= umax[:, None, :]) & (raw >= umin[:, None, :]), axis=1)
+    assert np.array_equal(L[:, :, 1:][inside], C[:, :, 1:][inside])
+    return int(limited.sum())
+
+
+@pytest.mark.parametrize("mname", ["delaunay", "square"])
+def test_limiter_properties_random(mname):
+    mesh = W.delaunay_mesh(400, 7) if mname == "delaunay" else W.square_mesh(14, 1.0, 0.2, 8)
+    orc = O.Oracle(mesh, 1)
+    C = rough_state(mesh.n_elem, 3)
+    L = orc.limit(C)
+    n_limited = check_limited(orc, mesh, C, L)
+    assert n_limited > 0.1 * mesh.n_elem * 4  # the limiter really acts here
+
+
+def test_limiter_properties_mild():
+    # small slopes: many elements already within bounds must stay unchanged
+    mesh = W.delaunay_mesh(400, 9)
+    orc = O.Oracle(mesh, 1)
+    C = W.random_state(mesh.n_elem, 3, seed=6)
+    L = orc.limit(C)
+    check_limited(orc, mesh, C, L)
+    assert np.sum(np.all(L == C, axis=2)) > 0.2 * mesh.n_elem * 4
+
+
+def test_limiter_properties_jump():
+    mesh = W.delaunay_mesh(500, 11)
+    orc = O.Oracle(mesh, 1)
+    C = orc.project(W.density_jump)
+    L = orc.limit(C)
+    assert check_limited(orc, mesh, C, L) > 0
+
+
+def test_limiter_idempotent():
+    mesh = W.delaunay_mesh(300, 5)
+    orc = O.Oracle(mesh, 1)
+    L = orc.limit(rough_state(mesh.n_elem, 4))
+    assert np.abs(orc.limit(L) - L).max() <= 1e-14 * np.abs(L).max()
+
+
+def test_limited_step_conserves_and_bounds():
+    mesh = W.delaunay_mesh(400, 12)
+    orc = O.Oracle(mesh, 1)
+    C = orc.project(W.density_jump)
+    dt, _ = orc.max_dt(C, 0.1)
+    det = orc.det()
+    C1 = orc.rk3_step(C, dt, limit=True)
+    tot0 = (det[:, None] * C[:, :, 0]).sum(0)
+    tot1 = (det[:, None] * C1[:, :, 0]).sum(0)
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * (det[:, None] * np.abs(C[:, :, 0])).sum(0))
+    # the last operation of the step is the limiter: its output is a fixed point
+    assert np.abs(orc.limit(C1) - C1).max() <= 1e-14 * np.abs(C1).max()
+
+
+def test_limiter_rejects_higher_order():
+    mesh = W.square_mesh(4, 1.0, 0.1, 0)
+    orc = O.Oracle(mesh, 2)
+    with pytest.raises(ValueError):
+        orc.limit(W.random_state(mesh.n_elem, orc.np, seed=0))

@@ -51,6 +51,11 @@ MUTANTS = {
     "vjp_pressure_velocity_term": ("ub += -g1 * rho * u * pb;\n    vb += -g1 * rho * v * pb;\n    /* u = U1", "ub += 0.0 * pb;\n    vb += -g1 * rho * v * pb;\n    /* u = U1"),
     "vjp_metric_not_transposed": ("Fxb[m] = adj[0][0] * Grb + adj[1][0] * Gsb;", "Fxb[m] = adj[0][0] * Grb + adj[0][1] * Gsb;"),
     "vjp_rk_stage_weight": ("u1b[x] = 0.25 * u2b[x] + 0.25 * dt * t[x];", "u1b[x] = 0.25 * u2b[x] + 0.75 * dt * t[x];"),
+    "limiter_min_branch_uses_max": ("ak = (umin - ub) / d;", "ak = (umax - ub) / d;"),
+    "limiter_scales_mean": ("for (int j = 1; j < np; ++j) C[(i * M + m) * np + j] *= alpha[i * M + m];",
+                            "for (int j = 0; j < np; ++j) C[(i * M + m) * np + j] *= alpha[i * M + m];"),
+    "limiter_last_point_not_min": ("if (ak < a) a = ak;", "a = ak;"),
+    "limiter_ignores_neighbours": ("const double un = cen[c->nbr[i * 3 + q] * M + m];", "const double un = ub;"),
 }
 
 
@@ -167,7 +172,21 @@ def pin_adjoint(lib):
     return bool(ok)
 
 
-PINS = [pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
+def pin_limiter(lib):
+    from test_oracle_limiter import check_limited, rough_state
+
+    mesh = W.delaunay_mesh(120, 7)
+    orc = O.Oracle(mesh, 1, lib=lib)
+    # one state where most elements are limited, one where many are not
+    for C in (rough_state(mesh.n_elem, 3), W.random_state(mesh.n_elem, 3, seed=4)):
+        try:
+            check_limited(orc, mesh, C, orc.limit(C))
+        except AssertionError:
+            return False
+    return True
+
+
+PINS = [pin_limiter, pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
 
 
 def run_pins(lib):
