@@ -227,6 +227,26 @@ int dg_quad_weights(dg_mesh m, double* w_dev, void* stream);
 enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1 };
 int dg_set_surface_mode(dg_mesh m, int mode);
 
+/* Slope limiting (Section "Limiting Kernel"): the Barth-Jespersen limiter
+ * for p = 1, each conserved variable separately.  With the centroid values
+ * of the element and of its three neighbours (for a linear function, its
+ * mean), Umax and Umin their extremes, and d = U(r_qk) - Ubar at each Gauss
+ * point of the element's sides, the factor alpha = min(1, min_k alpha_k)
+ * with alpha_k = (Umax - Ubar)/d (d > 0), (Umin - Ubar)/d (d < 0), 1 (d = 0)
+ * scales the two linear coefficients; the mean is unchanged.
+ *
+ * dg_limit applies it once, in place, to the internal-layout state C_dev
+ * (asynchronous on stream).  dg_set_limiter(m, DG_LIMITER_BJ) makes
+ * dg_rk_step, dg_rk_step_stages and dg_advance limit every RK stage's
+ * result and the new state, as the paper's time loop does;
+ * DG_LIMITER_NONE (the default) switches it off.  Errors: DG_EUNSUPPORTED
+ * for p != 1; with the limiter on, the edge-wise surface mode and
+ * dg_rk_step_vjp (the limited step is not differentiable) return
+ * DG_EUNSUPPORTED; DG_EINVAL for an unknown limiter. */
+enum { DG_LIMITER_NONE = 0, DG_LIMITER_BJ = 1 };
+int dg_set_limiter(dg_mesh m, int limiter);
+int dg_limit(dg_mesh m, double* C_dev, void* stream);
+
 /* Work-items per element in the element-wise kernels (forward right-hand
  * side and RK stages): 1 or 4.  With 4, lane m of a quad owns conserved
  * variable m for the modal contractions (all lanes walk the same points, so
@@ -258,7 +278,8 @@ enum {
     DG_KERNEL_DT = 3,       /* CFL reduction (both passes) */
     DG_KERNEL_STAGE = 4,    /* element-wise path: whole RHS (+ RK stage) in one kernel */
     DG_KERNEL_VJP = 5,      /* adjoint of the element-wise RHS (+ RK stage adjoint) */
-    DG_KERNEL_KINDS = 6
+    DG_KERNEL_LIMIT = 6,    /* slope limiter (p = 1) */
+    DG_KERNEL_KINDS = 7
 };
 int dg_timing_enable(dg_mesh m, int on);
 int dg_timing_read(dg_mesh m, double* ms, int64_t* count, int n);

@@ -51,6 +51,8 @@ EXPORTS = [
     "dg_quad_weights",
     "dg_set_lanes_per_element",
     "dg_set_surface_mode",
+    "dg_set_limiter",
+    "dg_limit",
     "dg_timing_enable",
     "dg_timing_read",
     "dg_reference_tables",
@@ -114,6 +116,8 @@ def load(path: str = LIB_PATH):
     lib.dg_quad_weights.argtypes = [_vp, _vp, _vp]
     lib.dg_set_lanes_per_element.argtypes = [_vp, i32]
     lib.dg_set_surface_mode.argtypes = [_vp, i32]
+    lib.dg_set_limiter.argtypes = [_vp, i32]
+    lib.dg_limit.argtypes = [_vp, _vp, _vp]
     lib.dg_timing_enable.argtypes = [_vp, i32]
     lib.dg_timing_read.argtypes = [_vp, _dp, ctypes.POINTER(i64), i32]
     lib.dg_reference_tables.argtypes = [i32, _dp, i64]
@@ -281,7 +285,7 @@ class DGMesh:
                                    ctypes.byref(host) if to_host else None, _ptr(ws), _stream(stream)))
         return dt_dev, (host.value if to_host else None)
 
-    KERNELS = ("traces", "edge", "element", "dt", "stage", "vjp")
+    KERNELS = ("traces", "edge", "element", "dt", "stage", "vjp", "limit")
     SURFACE_ELEMENTWISE = 0
     SURFACE_EDGEWISE = 1
 
@@ -291,6 +295,17 @@ class DGMesh:
 
     def set_surface_mode(self, mode: int):
         _check(self._lib.dg_set_surface_mode(self._h, int(mode)))
+
+    LIMITER_NONE, LIMITER_BJ = 0, 1
+
+    def set_limiter(self, limiter: int):
+        """0: no limiting; 1: Barth-Jespersen (p = 1) after every RK stage."""
+        _check(self._lib.dg_set_limiter(self._h, int(limiter)))
+
+    def limit(self, C, stream=None):
+        """Barth-Jespersen limiter (p = 1) applied once, in place; returns C."""
+        _check(self._lib.dg_limit(self._h, _ptr(C), _stream(stream)))
+        return C
 
     def timing(self, on: bool):
         _check(self._lib.dg_timing_enable(self._h, 1 if on else 0))

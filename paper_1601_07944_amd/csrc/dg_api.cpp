@@ -25,6 +25,7 @@ struct dg_mesh_s {
     std::vector<void*> allocs;
     // per-launch event timing (dg_timing_*)
     int surface = DG_SURFACE_ELEMENTWISE;
+    int limiter = DG_LIMITER_NONE;
     bool timing = false;
     struct Rec {
         int kind;
@@ -455,6 +456,13 @@ int dg_max_dt(dg_mesh m, const double* C, double cfl, double* dt_dev, double* dt
     return ok();
 }
 
+// the limiter after an RK stage, when the mesh has it switched on (the
+// paper limits every intermediate stage and the new time level)
+static void limit_stage(dg_mesh m, double* U, hipStream_t s)
+{
+    if (m->limiter == DG_LIMITER_BJ) timed(m, DG_KERNEL_LIMIT, s, [&] { dgk::launch_limit(m->dev, U, s); });
+}
+
 int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precision prec, void* ws, void* stream)
 {
     if (!m || !C || !ws) return fail(DG_EINVAL, "null argument");
@@ -469,11 +477,16 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
     double* u2 = (double*)(w + m->off_u2);
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
+    if (m->limiter != DG_LIMITER_NONE && m->surface != DG_SURFACE_ELEMENTWISE)
+        return fail(DG_EUNSUPPORTED, "the limiter needs the element-wise surface mode");
     if (m->surface == DG_SURFACE_ELEMENTWISE) {
         const bool mx = prec == DG_MIXED;
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, dt, dt_dev, s); });
+        limit_stage(m, u1, s);
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, mx, u1, C, u2, dt, dt_dev, s); });
+        limit_stage(m, u2, s);
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, mx, u2, nullptr, C, dt, dt_dev, s); });
+        limit_stage(m, C, s);
         return check_launch("dg_rk_step");
     }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s); });
@@ -504,6 +517,8 @@ int dg_advance(dg_mesh m, double* C, int64_t nsteps, double cfl, double* dt_dev,
     if (prec != DG_FP64 && prec != DG_MIXED) return fail(DG_EINVAL, "unknown precision %d", prec);
     if (prec == DG_MIXED && m->surface != DG_SURFACE_ELEMENTWISE)
         return fail(DG_EUNSUPPORTED, "DG_MIXED needs the element-wise surface mode");
+    if (m->limiter != DG_LIMITER_NONE && m->surface != DG_SURFACE_ELEMENTWISE)
+        return fail(DG_EUNSUPPORTED, "the limiter needs the element-wise surface mode");
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
     char* w = (char*)ws;
@@ -546,8 +561,11 @@ int dg_advance(dg_mesh m, double* C, int64_t nsteps, double cfl, double* dt_dev,
         dgk::FusedDt f3;
         f3.pout = part4;
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, 0.0, dt_dev, s, f1); });
+        limit_stage(m, u1, s);
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, mx, u1, C, u2, 0.0, dt_dev, s); });
+        limit_stage(m, u2, s);
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, mx, u2, nullptr, C, 0.0, dt_dev, s, f3); });
+        limit_stage(m, C, s);
     }
     return check_launch("dg_advance");
 }
@@ -560,8 +578,11 @@ int dg_rk_step_stages(dg_mesh m, double* C, double dt, const double* dt_dev, dou
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
     timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, false, C, nullptr, u1, dt, dt_dev, s); });
+    limit_stage(m, u1, s);
     timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, false, u1, C, u2, dt, dt_dev, s); });
+    limit_stage(m, u2, s);
     timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, false, u2, nullptr, C, dt, dt_dev, s); });
+    limit_stage(m, C, s);
     return check_launch("dg_rk_step_stages");
 }
 
@@ -570,6 +591,8 @@ int dg_rk_step_vjp(dg_mesh m, const double* C, double dt, const double* dt_dev, 
 {
     if (!m || !C || !ub || !Cb || !ws) return fail(DG_EINVAL, "null argument");
     if ((u1_in == nullptr) != (u2_in == nullptr)) return fail(DG_EINVAL, "pass both stage states or neither");
+    if (m->limiter != DG_LIMITER_NONE)
+        return fail(DG_EUNSUPPORTED, "the limited step is not differentiable; switch the limiter off");
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
     char* w = (char*)ws;
@@ -610,6 +633,26 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes)
     if (lanes != 0 && lanes != 1 && lanes != 4) return fail(DG_EINVAL, "lanes per element must be 0, 1 or 4");
     m->dev.lanes4 = lanes == 4 || (lanes == 0 && (m->dev.n <= DG_LANES4_MAX_ELEMENTS || m->dev.p >= 4));
     return ok();
+}
+
+int dg_set_limiter(dg_mesh m, int limiter)
+{
+    if (!m) return fail(DG_EINVAL, "null mesh");
+    if (limiter != DG_LIMITER_NONE && limiter != DG_LIMITER_BJ) return fail(DG_EINVAL, "unknown limiter %d", limiter);
+    if (limiter == DG_LIMITER_BJ && m->dev.p != 1)
+        return fail(DG_EUNSUPPORTED, "the Barth-Jespersen limiter is defined for p = 1 (this mesh has p = %d)", m->dev.p);
+    m->limiter = limiter;
+    return ok();
+}
+
+int dg_limit(dg_mesh m, double* C, void* stream)
+{
+    if (!m || !C) return fail(DG_EINVAL, "null argument");
+    if (m->dev.p != 1)
+        return fail(DG_EUNSUPPORTED, "the Barth-Jespersen limiter is defined for p = 1 (this mesh has p = %d)", m->dev.p);
+    hipStream_t s = (hipStream_t)stream;
+    timed(m, DG_KERNEL_LIMIT, s, [&] { dgk::launch_limit(m->dev, C, s); });
+    return check_launch("dg_limit");
 }
 
 int dg_set_surface_mode(dg_mesh m, int mode)

@@ -82,6 +82,8 @@ inline int stage4_partials(const MeshDev& m) { return m.npad / 64; }
 // final pass of the step-length reduction over `count` minima (also writes
 // dt_hist[0] when dt_hist is not null)
 void launch_dt_final(const double* partial, int count, double cfl, double* dt_dev, double* dt_hist, hipStream_t s);
+// Barth-Jespersen limiter of a p = 1 state, in place
+void launch_limit(const MeshDev& m, double* C, hipStream_t s);
 // first pass only (dt_partials(m) minima of 256 elements each)
 void launch_dt_partials_only(const MeshDev& m, const double* C, double* partial, hipStream_t s);
 // adjoint of the fused right-hand side / RK stages (modes of k_stage_vjp)

@@ -100,6 +100,12 @@ void launch_dt_final(const double* partial, int count, double cfl, double* dt_de
     k_dt_final<<<1, BLOCK, 0, s>>>(count, partial, cfl, dt_dev, dt_hist);
 }
 
+void launch_limit(const MeshDev& m, double* C, hipStream_t s)
+{
+    // the limiter is defined for p = 1 only (the caller checks)
+    k_limit_bj<1><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, C, m.side_nb, m.tab);
+}
+
 void launch_pack(const MeshDev& m, const double* Cu, double* C, hipStream_t s)
 {
     k_pack<<<grid_for(m.npad), BLOCK, 0, s>>>(m.n, m.npad, m.np, m.perm, Cu, C);
