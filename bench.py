@@ -49,21 +49,33 @@ def algorithmic_bytes_stage_kernel(n_elem: int, n_modes: int, stage0_reads: floa
     return per_elem * n_elem
 
 
+STAGE_SOURCE_END = "// ---------------------------------------------------------------- limiter"
+
+
+def stage_source_digest() -> str:
+    """sha256 prefix of what the stage kernels are compiled from: the kernel
+    header up to the limiter section (physics, helpers, the fused stage
+    kernels) and the compiler flags."""
+    import hashlib
+
+    from paper_1601_07944_amd import build as Bd
+
+    src = open(os.path.join(HERE, "paper_1601_07944_amd", "csrc", "dg_kernels.h")).read()
+    text = src[: src.index(STAGE_SOURCE_END)] + "\n".join(Bd.FLAGS)
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
 def load_traffic(kernel: str):
     """HBM bytes per launch measured with rocprofv3 counters, if the summary
-    in profiles/ was taken from the current kernel source."""
+    in profiles/ was taken from the current stage-kernel source."""
     path = os.path.join(HERE, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        import hashlib
-
         with open(path) as f:
             rec = json.load(f)
-        src = os.path.join(HERE, "paper_1601_07944_amd", "csrc", "dg_kernels.h")
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
         ent = rec.get(kernel)
-        if not ent or ent.get("source_sha256_16") != digest:
+        if not ent or ent.get("source_sha256_16") != stage_source_digest():
             return None
         return ent.get("bytes_per_launch")
     except Exception:
@@ -100,6 +112,52 @@ def cpu_baseline(mesh, p, seconds: float):
         "kind": "oracle",
         "sample": f"{steps} SSP-RK3 steps (+ CFL reduction) of the same {mesh.n_elem}-triangle p={p} vortex state, "
         f"{el:.1f} s wall",
+    }
+
+
+def limiter_overhead(steps: int):
+    """The paper's limiter benchmark (Section "Limiting"): p = 1 steps with
+    and without the Barth-Jespersen limiter after every RK stage, here on
+    128 x 128 x 2 = 32,768 jittered triangles of the unit square with the
+    density jump across r < 0.25 (a discontinuity the limiter acts on)."""
+    import numpy as np
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+    from paper_1601_07944_amd import workloads as W
+
+    mesh = W.square_mesh(128, 1.0, 0.2, 5)
+    dm = B.DGMesh.from_mesh(mesh, 1)
+    xy = dm.quad_points().cpu().numpy()
+    C0 = dm.project(torch.from_numpy(np.ascontiguousarray(W.density_jump(xy[..., 0], xy[..., 1]))).cuda())
+    ws = dm.workspace("step")
+    dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, lim in (("unlimited", B.DGMesh.LIMITER_NONE), ("limited", B.DGMesh.LIMITER_BJ)):
+        dm.set_limiter(lim)
+        C = C0.clone()
+        dm.advance(C, 5, 0.1, dt_dev=dt_dev, ws=ws)
+        torch.cuda.synchronize()
+        e0.record()
+        dm.advance(C, steps, 0.1, dt_dev=dt_dev, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / steps
+    dm.timing(True)
+    dm.advance(C0.clone(), 10, 0.1, dt_dev=dt_dev, ws=ws)
+    torch.cuda.synchronize()
+    dm.timing(False)
+    kt = dm.timing_read()
+    dm.close()
+    return {
+        "workload": "density jump, periodic unit square, 32,768 jittered triangles, p=1, CFL 0.1",
+        "steps": steps,
+        "ms_per_step_unlimited": res["unlimited"],
+        "ms_per_step_limited": res["limited"],
+        "overhead": res["limited"] / res["unlimited"] - 1.0,
+        "limit_kernel_us": kt["limit"][0] / max(1, kt["limit"][1]) * 1e3,
     }
 
 
@@ -406,6 +464,8 @@ def main():
     ms_step_edge = e0.elapsed_time(e1) / args.steps
     dm.set_surface_mode(dm.SURFACE_ELEMENTWISE)
 
+    limiter = limiter_overhead(args.steps)
+
     out = {
         "metric": METRIC,
         "value": dof * 3 / (ms_step * 1e-3),
@@ -459,6 +519,7 @@ def main():
             "ms_reverse": ms_rev,
         },
     }
+    out["limiter_overhead"] = limiter
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
