@@ -898,6 +898,8 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
 // for d > 0, (Umin - Ubar) / d for d < 0, and 1 for d = 0; the smallest
 // factor, at most 1, scales modes 1 and 2.  Only those modes are written, so
 // reading the neighbours' means while other work-items limit is race-free.
+// Four work-items per element (one per variable) give a p = 1 mesh enough
+// wavefronts to fill the GPU.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_limit_bj(int n, double* __restrict__ C, const int* __restrict__ snb,
                                                     const double* __restrict__ tab)
@@ -905,38 +907,34 @@ __global__ __launch_bounds__(BLOCK) void k_limit_bj(int n, double* __restrict__ 
     using O = Ord<P>;
     constexpr int NP = O::NP, NE = O::NE;
     const double s2 = 1.4142135623730951;
-    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    // four work-items per element, one per conserved variable
+    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    const int e = t >> 2, m = t & 3;
     if (e >= n) return;
-    const int so = state_off(e, 4 * NP);
-    int nbo[3];
+    const int so = state_off(e, 4 * NP) + m * NP * LANES;
+    double c[NP];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) nbo[q] = state_off(snb[state_off(e, 3) + q * LANES], 4 * NP);
+    for (int j = 0; j < NP; ++j) c[j] = C[so + j * LANES];
+    const double ub = s2 * c[0];
+    double umax = ub, umin = ub;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        double c[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) c[j] = C[so + (m * NP + j) * LANES];
-        const double ub = s2 * c[0];
-        double umax = ub, umin = ub;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const double un = s2 * C[nbo[q] + m * NP * LANES];
-            umax = fmax(umax, un);
-            umin = fmin(umin, un);
-        }
-        double a = 1.0;
-#pragma unroll
-        for (int qk = 0; qk < 3 * NE; ++qk) {
-            double u = 0.0;
-#pragma unroll
-            for (int j = 0; j < NP; ++j) u = fma(tab[O::PHS + qk * NP + j], c[j], u);
-            const double d = u - ub;
-            const double ak = d > 0.0 ? (umax - ub) / d : d < 0.0 ? (umin - ub) / d : 1.0;
-            a = fmin(a, ak);
-        }
-#pragma unroll
-        for (int j = 1; j < NP; ++j) C[so + (m * NP + j) * LANES] = a * c[j];
+    for (int q = 0; q < 3; ++q) {
+        const double un = s2 * C[state_off(snb[state_off(e, 3) + q * LANES], 4 * NP) + m * NP * LANES];
+        umax = fmax(umax, un);
+        umin = fmin(umin, un);
     }
+    double a = 1.0;
+#pragma unroll
+    for (int qk = 0; qk < 3 * NE; ++qk) {
+        double u = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) u = fma(tab[O::PHS + qk * NP + j], c[j], u);
+        const double d = u - ub;
+        const double ak = d > 0.0 ? (umax - ub) / d : d < 0.0 ? (umin - ub) / d : 1.0;
+        a = fmin(a, ak);
+    }
+#pragma unroll
+    for (int j = 1; j < NP; ++j) C[so + j * LANES] = a * c[j];
 }
 
 // ---------------------------------------------------------------- adjoint
