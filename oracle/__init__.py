@@ -70,6 +70,8 @@ def _configure(lib):
     lib.orc_limit_bj.restype = ctypes.c_int
     lib.orc_rk3_step_limited.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
     lib.orc_rk3_step_limited.restype = ctypes.c_int
+    lib.orc_rk_step.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    lib.orc_rk_step.restype = ctypes.c_int
     lib.orc_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
     _cp = ctypes.POINTER(ctypes.c_double * 2)
     lib.orc_cs_rhs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -264,6 +266,16 @@ class Oracle:
                 raise ValueError("the limiter is defined for p = 1 only")
         else:
             self._lib.orc_rk3_step(self._ctx, _p(C), float(dt))
+        return C
+
+    def rk_step(self, C, dt, scheme, limit=False):
+        """One step of the paper's classic RK integrators: scheme "rk2"
+        (Heun) or "rk4"; "ssp3" is rk3_step."""
+        if scheme == "ssp3":
+            return self.rk3_step(C, dt, limit)
+        C = self._state(C).copy()
+        if self._lib.orc_rk_step(self._ctx, _p(C), float(dt), {"rk2": 1, "rk4": 2}[scheme], int(limit)) != 0:
+            raise ValueError("unsupported scheme / limiter combination")
         return C
 
     def limit(self, C):

@@ -23,6 +23,7 @@
  *     in opposite directions);
  *   - L2 projection onto the orthonormal basis (mass matrix = det J * I);
  *   - three-stage SSP Runge-Kutta in Shu-Osher form and a CFL time step;
+ *   - the paper's classic second- and fourth-order Runge-Kutta steps;
  *   - the Barth-Jespersen slope limiter for p = 1 (Section "Limiting
  *     Kernel"), optionally applied after every RK stage.
  *
@@ -453,6 +454,58 @@ int orc_rk3_step_limited(const orc_ctx *c, double *C, double dt)
     free(L);
     free(u1);
     free(u2);
+    return 0;
+}
+
+/* The paper's classic explicit Runge-Kutta integrators (Section
+ * "Time-stepping"), one step in place, optionally limited like
+ * orc_rk3_step_limited (each stage's solution and the new state):
+ *   scheme 1, second order (Heun):  u1 = u + dt L(u);
+ *                                   u  = u/2 + (u1 + dt L(u1))/2
+ *   scheme 2, fourth order:  k1 = L(u), k2 = L(u + dt/2 k1),
+ *                            k3 = L(u + dt/2 k2), k4 = L(u + dt k3),
+ *                            u  = u + dt (k1 + 2 k2 + 2 k3 + k4) / 6
+ * Returns -1 for an unknown scheme or a limiter request at p != 1. */
+int orc_rk_step(const orc_ctx *c, double *C, double dt, int scheme, int limit)
+{
+    if (scheme != 1 && scheme != 2) return -1;
+    if (limit && c->p != 1) return -1;
+    size_t len = (size_t)c->n * M * c->np;
+    double *L = (double *)malloc(sizeof(double) * len);
+    double *U = (double *)malloc(sizeof(double) * len);
+    if (scheme == 1) {
+        orc_rhs(c, C, L);
+        for (size_t x = 0; x < len; ++x) U[x] = C[x] + dt * L[x];
+        if (limit) orc_limit_bj(c, U);
+        orc_rhs(c, U, L);
+        for (size_t x = 0; x < len; ++x) C[x] = 0.5 * C[x] + 0.5 * (U[x] + dt * L[x]);
+    } else {
+        double *K = (double *)malloc(sizeof(double) * len); /* k1 + 2 k2 + 2 k3 so far */
+        orc_rhs(c, C, L);
+        for (size_t x = 0; x < len; ++x) {
+            K[x] = L[x];
+            U[x] = C[x] + 0.5 * dt * L[x];
+        }
+        if (limit) orc_limit_bj(c, U);
+        orc_rhs(c, U, L);
+        for (size_t x = 0; x < len; ++x) {
+            K[x] += 2.0 * L[x];
+            U[x] = C[x] + 0.5 * dt * L[x];
+        }
+        if (limit) orc_limit_bj(c, U);
+        orc_rhs(c, U, L);
+        for (size_t x = 0; x < len; ++x) {
+            K[x] += 2.0 * L[x];
+            U[x] = C[x] + dt * L[x];
+        }
+        if (limit) orc_limit_bj(c, U);
+        orc_rhs(c, U, L);
+        for (size_t x = 0; x < len; ++x) C[x] = C[x] + dt * (K[x] + L[x]) / 6.0;
+        free(K);
+    }
+    if (limit) orc_limit_bj(c, C);
+    free(L);
+    free(U);
     return 0;
 }
 

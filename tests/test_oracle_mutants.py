@@ -56,6 +56,11 @@ MUTANTS = {
                             "for (int j = 0; j < np; ++j) C[(i * M + m) * np + j] *= alpha[i * M + m];"),
     "limiter_last_point_not_min": ("if (ak < a) a = ak;", "a = ak;"),
     "limiter_ignores_neighbours": ("const double un = cen[c->nbr[i * 3 + q] * M + m];", "const double un = ub;"),
+    "rk4_k2_weight": ("K[x] += 2.0 * L[x];\n            U[x] = C[x] + 0.5 * dt * L[x];",
+                      "K[x] += 1.0 * L[x];\n            U[x] = C[x] + 0.5 * dt * L[x];"),
+    "rk4_last_stage_full_step": ("U[x] = C[x] + dt * L[x];\n        }\n        if (limit) orc_limit_bj(c, U);\n        orc_rhs(c, U, L);\n        for (size_t x = 0; x < len; ++x) C[x] = C[x] + dt * (K[x] + L[x]) / 6.0;",
+                                 "U[x] = C[x] + 0.5 * dt * L[x];\n        }\n        if (limit) orc_limit_bj(c, U);\n        orc_rhs(c, U, L);\n        for (size_t x = 0; x < len; ++x) C[x] = C[x] + dt * (K[x] + L[x]) / 6.0;"),
+    "rk2_weights": ("C[x] = 0.5 * C[x] + 0.5 * (U[x] + dt * L[x]);", "C[x] = 0.25 * C[x] + 0.75 * (U[x] + dt * L[x]);"),
 }
 
 
@@ -186,7 +191,26 @@ def pin_limiter(lib):
     return True
 
 
-PINS = [pin_limiter, pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
+def pin_rk(lib):
+    mesh = W.square_mesh(5, 10.0, 0.1, 2)
+    orc = O.Oracle(mesh, 1, lib=lib)
+    C0 = orc.project(W.isentropic_vortex)
+    T = 0.4
+    ok = True
+    for scheme, order in (("rk2", 2), ("rk4", 4)):
+        def run(n):
+            C = C0.copy()
+            for _ in range(n):
+                C = orc.rk_step(C, T / n, scheme)
+            return C
+
+        ref = run(128)
+        e = [np.abs(run(n) - ref).max() for n in (4, 8)]
+        ok &= abs(math.log2(e[0] / e[1]) - order) < 0.4
+    return bool(ok)
+
+
+PINS = [pin_rk, pin_limiter, pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
 
 
 def run_pins(lib):
