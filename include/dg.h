@@ -227,6 +227,21 @@ int dg_quad_weights(dg_mesh m, double* w_dev, void* stream);
 enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1 };
 int dg_set_surface_mode(dg_mesh m, int mode);
 
+/* Time integrator of dg_rk_step and dg_advance: DG_RK_SSP3 (default; the
+ * three-stage SSP scheme of dg_rk_step's comment), or the paper's classic
+ * explicit Runge-Kutta schemes of order two and four (Section
+ * "Time-stepping"): DG_RK2, Heun's method, u1 = u + dt L(u),
+ * u = u/2 + (u1 + dt L(u1))/2; DG_RK4, the classic four-stage scheme,
+ * u = u + dt (k1 + 2 k2 + 2 k3 + k4)/6 with k1 = L(u), k2 = L(u + dt/2 k1),
+ * k3 = L(u + dt/2 k2), k4 = L(u + dt k3).  Every stage is one fused kernel
+ * (RK4 keeps its running sum in the step workspace).  With RK2 / RK4,
+ * dg_advance computes each step's length with a separate reduction, and
+ * dg_rk_step_stages and dg_rk_step_vjp return DG_EUNSUPPORTED (their stage
+ * states and adjoint are SSP-RK3's), as does the edge-wise surface mode.
+ * DG_EINVAL for an unknown scheme. */
+enum { DG_RK_SSP3 = 0, DG_RK2 = 1, DG_RK4 = 2 };
+int dg_set_integrator(dg_mesh m, int scheme);
+
 /* Slope limiting (Section "Limiting Kernel"): the Barth-Jespersen limiter
  * for p = 1, each conserved variable separately.  With the centroid values
  * of the element and of its three neighbours (for a linear function, its

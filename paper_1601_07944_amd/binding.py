@@ -51,6 +51,7 @@ EXPORTS = [
     "dg_quad_weights",
     "dg_set_lanes_per_element",
     "dg_set_surface_mode",
+    "dg_set_integrator",
     "dg_set_limiter",
     "dg_limit",
     "dg_timing_enable",
@@ -116,6 +117,7 @@ def load(path: str = LIB_PATH):
     lib.dg_quad_weights.argtypes = [_vp, _vp, _vp]
     lib.dg_set_lanes_per_element.argtypes = [_vp, i32]
     lib.dg_set_surface_mode.argtypes = [_vp, i32]
+    lib.dg_set_integrator.argtypes = [_vp, i32]
     lib.dg_set_limiter.argtypes = [_vp, i32]
     lib.dg_limit.argtypes = [_vp, _vp, _vp]
     lib.dg_timing_enable.argtypes = [_vp, i32]
@@ -295,6 +297,12 @@ class DGMesh:
 
     def set_surface_mode(self, mode: int):
         _check(self._lib.dg_set_surface_mode(self._h, int(mode)))
+
+    RK_SSP3, RK2, RK4 = 0, 1, 2
+
+    def set_integrator(self, scheme: int):
+        """dg_rk_step / dg_advance scheme: 0 SSP-RK3, 1 Heun (RK2), 2 classic RK4."""
+        _check(self._lib.dg_set_integrator(self._h, int(scheme)))
 
     LIMITER_NONE, LIMITER_BJ = 0, 1
 

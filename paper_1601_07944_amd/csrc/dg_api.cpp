@@ -26,6 +26,8 @@ struct dg_mesh_s {
     // per-launch event timing (dg_timing_*)
     int surface = DG_SURFACE_ELEMENTWISE;
     int limiter = DG_LIMITER_NONE;
+    int integrator = DG_RK_SSP3;
+    size_t off_acc = 0;  // RK4 accumulator state in the step workspace
     bool timing = false;
     struct Rec {
         int kind;
@@ -313,7 +315,8 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     m->off_u2 = 3 * trace + part + state;
     m->off_part4 = 3 * trace + part + 2 * state;
     const size_t part4 = align256((size_t)dgk::stage4_partials(d) * 8);
-    m->ws_step = (int64_t)(3 * trace + part + 2 * state + part4);
+    m->off_acc = 3 * trace + part + 2 * state + part4;
+    m->ws_step = (int64_t)(3 * trace + part + 3 * state + part4);
     m->state_bytes = state;
     m->ws_vjp = (int64_t)(4 * state);
     *out = m;
@@ -479,6 +482,52 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
     const dgk::MeshDev& d = m->dev;
     if (m->limiter != DG_LIMITER_NONE && m->surface != DG_SURFACE_ELEMENTWISE)
         return fail(DG_EUNSUPPORTED, "the limiter needs the element-wise surface mode");
+    if (m->integrator != DG_RK_SSP3 && m->surface != DG_SURFACE_ELEMENTWISE)
+        return fail(DG_EUNSUPPORTED, "RK2 / RK4 need the element-wise surface mode");
+    if (m->integrator == DG_RK2) {
+        // Heun: u1 = u + dt L(u);  u = 1/2 u + 1/2 (u1 + dt L(u1))
+        const bool mx = prec == DG_MIXED;
+        dgk::StageGen g2;
+        g2.a = 0.5;
+        g2.b = 0.5;
+        g2.g = 0.5;  // X = the output (stage-0) state itself
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, dt, dt_dev, s); });
+        limit_stage(m, u1, s);
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, u1, C, dt, dt_dev, g2, s); });
+        limit_stage(m, C, s);
+        return check_launch("dg_rk_step");
+    }
+    if (m->integrator == DG_RK4) {
+        // classic RK4 with the running sum S = u + dt (k1 + 2 k2 + 2 k3) / 6
+        const bool mx = prec == DG_MIXED;
+        double* S4 = (double*)(w + m->off_acc);
+        dgk::StageGen g;
+        g.b = 1.0;
+        g.g = 0.5;
+        g.S = S4;
+        g.d = 1.0 / 6.0;
+        g.s_init = 1;  // u1 = u + dt/2 k1, S = u + dt/6 k1
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, C, u1, dt, dt_dev, g, s); });
+        limit_stage(m, u1, s);
+        g = dgk::StageGen();
+        g.a = 1.0;
+        g.X = C;
+        g.g = 0.5;
+        g.S = S4;
+        g.d = 1.0 / 3.0;  // u2 = u + dt/2 k2, S += dt/3 k2
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, u1, u2, dt, dt_dev, g, s); });
+        limit_stage(m, u2, s);
+        g.g = 1.0;  // u3 = u + dt k3, S += dt/3 k3 (u3 reuses u1)
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, u2, u1, dt, dt_dev, g, s); });
+        limit_stage(m, u1, s);
+        g = dgk::StageGen();
+        g.a = 1.0;
+        g.X = S4;
+        g.g = 1.0 / 6.0;  // u = S + dt/6 k4
+        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, u1, C, dt, dt_dev, g, s); });
+        limit_stage(m, C, s);
+        return check_launch("dg_rk_step");
+    }
     if (m->surface == DG_SURFACE_ELEMENTWISE) {
         const bool mx = prec == DG_MIXED;
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, dt, dt_dev, s); });
@@ -524,7 +573,7 @@ int dg_advance(dg_mesh m, double* C, int64_t nsteps, double cfl, double* dt_dev,
     char* w = (char*)ws;
     double* part = (double*)(w + m->off_part);
     double* part4 = (double*)(w + m->off_part4);
-    if (m->surface != DG_SURFACE_ELEMENTWISE || !d.lanes4) {
+    if (m->surface != DG_SURFACE_ELEMENTWISE || !d.lanes4 || m->integrator != DG_RK_SSP3) {
         // separate reduction each step
         for (int64_t k = 0; k < nsteps; ++k) {
             timed(m, DG_KERNEL_DT, s, [&] {
@@ -574,6 +623,7 @@ int dg_rk_step_stages(dg_mesh m, double* C, double dt, const double* dt_dev, dou
                       void* stream)
 {
     if (!m || !C || !u1 || !u2) return fail(DG_EINVAL, "null argument");
+    if (m->integrator != DG_RK_SSP3) return fail(DG_EUNSUPPORTED, "the stage states are those of SSP-RK3");
     (void)ws;
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
@@ -593,6 +643,7 @@ int dg_rk_step_vjp(dg_mesh m, const double* C, double dt, const double* dt_dev, 
     if ((u1_in == nullptr) != (u2_in == nullptr)) return fail(DG_EINVAL, "pass both stage states or neither");
     if (m->limiter != DG_LIMITER_NONE)
         return fail(DG_EUNSUPPORTED, "the limited step is not differentiable; switch the limiter off");
+    if (m->integrator != DG_RK_SSP3) return fail(DG_EUNSUPPORTED, "the step adjoint is that of SSP-RK3");
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
     char* w = (char*)ws;
@@ -632,6 +683,15 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes)
     if (!m) return fail(DG_EINVAL, "null mesh");
     if (lanes != 0 && lanes != 1 && lanes != 4) return fail(DG_EINVAL, "lanes per element must be 0, 1 or 4");
     m->dev.lanes4 = lanes == 4 || (lanes == 0 && (m->dev.n <= DG_LANES4_MAX_ELEMENTS || m->dev.p >= 4));
+    return ok();
+}
+
+int dg_set_integrator(dg_mesh m, int scheme)
+{
+    if (!m) return fail(DG_EINVAL, "null mesh");
+    if (scheme != DG_RK_SSP3 && scheme != DG_RK2 && scheme != DG_RK4)
+        return fail(DG_EINVAL, "unknown integrator %d", scheme);
+    m->integrator = scheme;
     return ok();
 }
 

@@ -75,8 +75,22 @@ void launch_element(const MeshDev& m, int mode, const double* C, const double* U
 // fused right-hand side / SSP-RK3 stage (element-wise surface integral);
 // mode as for launch_element, except that mode 3 updates `out` in place
 // (it is the stage-0 state) and U0 must be nullptr
+// A stage of a general explicit Runge-Kutta scheme (stage kernels' mode 4),
+// with U the stage's input state and L = L(U):
+//   out = a X + b U + g h L,  X = the array X, or `out` itself when X is null
+//   (read before it is overwritten, as mode 3 reads the stage-0 state);
+//   if S is set: S = (s_init ? U : S) + d h L  (an accumulator, e.g. RK4's
+//   running sum of weighted stage derivatives).
+struct StageGen {
+    double a = 0.0, b = 0.0, g = 0.0, d = 0.0;
+    const double* X = nullptr;
+    double* S = nullptr;
+    int s_init = 0;
+};
 void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out, double dt,
                   const double* dt_dev, hipStream_t s, const FusedDt& fz = FusedDt());
+void launch_stage_general(const MeshDev& m, bool mixed, const double* C, double* out, double dt,
+                          const double* dt_dev, const StageGen& gs, hipStream_t s);
 // number of per-block minima a 4-lane stage 3 writes (one per 64 elements)
 inline int stage4_partials(const MeshDev& m) { return m.npad / 64; }
 // final pass of the step-length reduction over `count` minima (also writes

@@ -368,6 +368,16 @@ __device__ __forceinline__ double dt_from_partials(const double* __restrict__ pi
 // possible side addresses fall in different banks); tables indexed by the
 // element's own side or volume point are uniform and go through scalar loads.
 
+// the stage combination of MODE 4 (StageGen) for one coefficient (x: its
+// index)
+__device__ __forceinline__ double stage_general(const StageGen& gs, double cs, double h, double L, int x,
+                                                const double* out)
+{
+    const double xv = gs.a == 0.0 ? 0.0 : (gs.X ? gs.X[x] : out[x]);
+    if (gs.S) gs.S[x] = (gs.s_init ? cs : gs.S[x]) + (gs.d * h) * L;
+    return gs.a * xv + gs.b * cs + (gs.g * h) * L;
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs; remap them so that each
 // XCD works on one contiguous range of the space-filling-curve order and
 // neighbour gathers stay in that XCD's L2.
@@ -395,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
                                                  const int* __restrict__ snb, const int* __restrict__ sside,
                                                  const double* __restrict__ sgeo, const T* __restrict__ tab,
                                                  const double* __restrict__ tab64, double gamma, double dt,
-                                                 const double* __restrict__ dt_dev)
+                                                 const double* __restrict__ dt_dev, StageGen gs)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
@@ -526,8 +536,10 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
                     out[x] = cs + h * L;
                 } else if constexpr (MODE == 2) {
                     out[x] = 0.75 * U0[x] + 0.25 * (cs + h * L);
-                } else {
+                } else if constexpr (MODE == 3) {
                     out[x] = (1.0 / 3.0) * out[x] + (2.0 / 3.0) * (cs + h * L);
+                } else {
+                    out[x] = stage_general(gs, cs, h, L, x, out);
                 }
             }
         }
@@ -807,7 +819,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
                                                   double gamma, double dt, const double* __restrict__ dt_dev,
                                                   const double* __restrict__ pin, int pin_count, double cfl,
                                                   double* __restrict__ dt_store, double* __restrict__ dt_hist,
-                                                  double* __restrict__ pout)
+                                                  double* __restrict__ pout, StageGen gs)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NE = O::NE;
@@ -867,8 +879,10 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
                     v = cs + h * L;
                 } else if constexpr (MODE == 2) {
                     v = 0.75 * U0[x] + 0.25 * (cs + h * L);
-                } else {
+                } else if constexpr (MODE == 3) {
                     v = (1.0 / 3.0) * out[x] + (2.0 / 3.0) * (cs + h * L);
+                } else {
+                    v = stage_general(gs, cs, h, L, x, out);
                 }
             }
             out[x] = v;
@@ -1461,32 +1475,35 @@ struct Launch {
 #undef DG_ELEM
     }
     static void stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out,
-                      double dt, const double* dt_dev, hipStream_t s, const FusedDt& fz = FusedDt())
+                      double dt, const double* dt_dev, hipStream_t s, const FusedDt& fz = FusedDt(),
+                      const StageGen& gs = StageGen())
     {
         const int nb = (m.npad + BLOCK - 1) / BLOCK;
         dim3 g((nb + 7) / 8 * 8);
 #define DG_STAGE(MODE, T, TAB)                                                                                  \
     k_stage<P, MODE, T><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, TAB, \
-                                            m.tab, m.gamma, dt, dt_dev)
+                                            m.tab, m.gamma, dt, dt_dev, gs)
         if (m.lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
 #define DG_STAGE4(MODE, T, TAB)                                                                                  \
     k_stage4<P, MODE, T><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, TAB, \
                                               m.tab, m.gamma, dt, dt_dev, fz.pin, fz.pin_count, fz.cfl,          \
-                                              fz.dt_store, fz.dt_hist, fz.pout)
+                                              fz.dt_store, fz.dt_hist, fz.pout, gs)
             if (mixed) {
                 switch (mode) {
                 case 0: DG_STAGE4(0, float, m.tab32); break;
                 case 1: DG_STAGE4(1, float, m.tab32); break;
                 case 2: DG_STAGE4(2, float, m.tab32); break;
-                default: DG_STAGE4(3, float, m.tab32); break;
+                case 3: DG_STAGE4(3, float, m.tab32); break;
+                default: DG_STAGE4(4, float, m.tab32); break;
                 }
             } else {
                 switch (mode) {
                 case 0: DG_STAGE4(0, double, m.tab); break;
                 case 1: DG_STAGE4(1, double, m.tab); break;
                 case 2: DG_STAGE4(2, double, m.tab); break;
-                default: DG_STAGE4(3, double, m.tab); break;
+                case 3: DG_STAGE4(3, double, m.tab); break;
+                default: DG_STAGE4(4, double, m.tab); break;
                 }
             }
 #undef DG_STAGE4
@@ -1497,14 +1514,16 @@ struct Launch {
             case 0: DG_STAGE(0, float, m.tab32); break;
             case 1: DG_STAGE(1, float, m.tab32); break;
             case 2: DG_STAGE(2, float, m.tab32); break;
-            default: DG_STAGE(3, float, m.tab32); break;
+            case 3: DG_STAGE(3, float, m.tab32); break;
+            default: DG_STAGE(4, float, m.tab32); break;
             }
         } else {
             switch (mode) {
             case 0: DG_STAGE(0, double, m.tab); break;
             case 1: DG_STAGE(1, double, m.tab); break;
             case 2: DG_STAGE(2, double, m.tab); break;
-            default: DG_STAGE(3, double, m.tab); break;
+            case 3: DG_STAGE(3, double, m.tab); break;
+            default: DG_STAGE(4, double, m.tab); break;
             }
         }
 #undef DG_STAGE

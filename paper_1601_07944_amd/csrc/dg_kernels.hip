@@ -69,6 +69,12 @@ void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const
     DG_DISPATCH_P(m.p, stage(m, mode, mixed, C, U0, out, dt, dt_dev, s, fz));
 }
 
+void launch_stage_general(const MeshDev& m, bool mixed, const double* C, double* out, double dt,
+                          const double* dt_dev, const StageGen& gs, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, stage(m, 4, mixed, C, nullptr, out, dt, dt_dev, s, FusedDt(), gs));
+}
+
 void launch_stage_vjp(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X, const double* Y,
                       double* out, double dt, const double* dt_dev, hipStream_t s)
 {
