@@ -72,6 +72,7 @@ def _configure(lib):
     lib.orc_rk3_step_limited.restype = ctypes.c_int
     lib.orc_rk_step.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int]
     lib.orc_rk_step.restype = ctypes.c_int
+    lib.orc_set_bc_state.argtypes = [ctypes.c_void_p, _dp]
     lib.orc_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
     _cp = ctypes.POINTER(ctypes.c_double * 2)
     lib.orc_cs_rhs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -169,6 +170,7 @@ class Oracle:
         )
         if not ctx:
             raise ValueError("oracle: unsupported order")
+        self.has_boundary = bool((mesh.nbr_elem < 0).any())
         self._ctx = ctypes.c_void_p(ctx)
         self._lib = lib
 
@@ -198,8 +200,16 @@ class Oracle:
         self._lib.orc_cs_rhs(self._ctx, C.ctypes.data, R.ctypes.data)
         return R
 
+    def set_bc_state(self, U):
+        """Conserved state (rho, rho u, rho v, E) of boundary code -3."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (4,)
+        self._lib.orc_set_bc_state(self._ctx, _p(U))
+
     def rhs_vjp(self, C, Rbar):
-        """Hand-written adjoint: (dR/dC)^T Rbar."""
+        """Hand-written adjoint: (dR/dC)^T Rbar (periodic meshes)."""
+        if self.has_boundary:
+            raise NotImplementedError("the oracle's adjoint covers periodic meshes only")
         C = self._state(C)
         Rbar = self._state(Rbar)
         Cb = np.empty_like(C)
@@ -207,7 +217,9 @@ class Oracle:
         return Cb
 
     def rk3_step_vjp(self, C, dt, ubar):
-        """Adjoint of one SSP-RK3 step with fixed dt."""
+        """Adjoint of one SSP-RK3 step with fixed dt (periodic meshes)."""
+        if self.has_boundary:
+            raise NotImplementedError("the oracle's adjoint covers periodic meshes only")
         C = self._state(C)
         ubar = self._state(ubar)
         Cb = np.empty_like(C)

@@ -74,6 +74,8 @@ typedef struct {
     double *dr_v;  /* [nq][np] */
     double *ds_v;  /* [nq][np] */
     double *phi_s; /* [3][ne][np] */
+    double bc_state[M]; /* state of boundary code -3 */
+    int has_bc;         /* some side is a domain boundary (negative code) */
 } orc_ctx;
 
 /* ---------------------------------------------------------------- basis */
@@ -168,6 +170,8 @@ orc_ctx *orc_create(int p, int64_t n, const double *vxy, const int64_t *nbr, con
     memcpy(c->nbr, nbr, sizeof(int64_t) * 3 * n);
     c->nbs = (int8_t *)malloc(3 * n);
     memcpy(c->nbs, nbs, 3 * n);
+    for (int64_t x = 0; x < 3 * n; ++x)
+        if (nbr[x] < 0) c->has_bc = 1;
     c->qr = (double *)malloc(sizeof(double) * nq);
     c->qs = (double *)malloc(sizeof(double) * nq);
     c->qw = (double *)malloc(sizeof(double) * nq);
@@ -191,6 +195,12 @@ orc_ctx *orc_create(int p, int64_t n, const double *vxy, const int64_t *nbr, con
             orc_basis(p, r, s, c->phi_s + (q * ne + k) * np, NULL, NULL);
         }
     return c;
+}
+
+/* state of boundary code -3 (conserved variables) */
+void orc_set_bc_state(orc_ctx *c, const double *U)
+{
+    for (int m = 0; m < M; ++m) c->bc_state[m] = U[m];
 }
 
 void orc_destroy(orc_ctx *c)
@@ -377,7 +387,8 @@ void orc_rk3_step(const orc_ctx *c, double *C, double dt)
 /* Barth-Jespersen slope limiter for p = 1 (Section "Limiting Kernel", eqs.
  * (limit), (limitmax), (limitmin)), each conserved variable separately:
  *   - centroid values: U_i at its own centroid (1/3, 1/3) and each
- *     neighbour's U at its own centroid, all from the input state;
+ *     neighbour's U at its own centroid, all from the input state (a side
+ *     on the domain boundary contributes no neighbour);
  *   - Umax, Umin: the largest and smallest of the four;
  *   - at every Gauss point r_qk of the element's three sides, with
  *     d = U_i(r_qk) - U_i(centroid): alpha_k = min(1, (Umax - U_i(centroid)) / d)
@@ -404,6 +415,7 @@ int orc_limit_bj(const orc_ctx *c, double *C)
             const double ub = cen[i * M + m];
             double umax = ub, umin = ub;
             for (int q = 0; q < 3; ++q) {
+                if (c->nbr[i * 3 + q] < 0) continue; /* a domain boundary: no neighbour */
                 const double un = cen[c->nbr[i * 3 + q] * M + m];
                 if (un > umax) umax = un;
                 if (un < umin) umin = un;

@@ -109,6 +109,110 @@ def square_mesh(n: int, length: float = 1.0, jitter: float = 0.0, seed: int = 0)
     return Mesh(vxy, nbr, nsd, length, name=f"square{n}x{n}x2_j{jitter}_s{seed}")
 
 
+# boundary codes in place of a neighbour (Section "Mesh Connectivity":
+# boundary edges store a negative integer naming their kind of boundary)
+BC_WALL, BC_OUTFLOW, BC_STATE = -1, -2, -3
+
+
+def box_mesh(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0, jitter: float = 0.0, seed: int = 0,
+             bc=(BC_WALL, BC_WALL, 0, 0)) -> Mesh:
+    """nx x ny lattice on [0, lx] x [0, ly], each square split along the
+    diagonal (i, j) -> (i+1, j+1) as in square_mesh.  bc = (left, right,
+    bottom, top): a negative boundary code for each side of the box, or 0 on
+    both sides of a direction for periodicity in it.  Interior vertices are
+    jittered by U[-jitter*h, jitter*h] per coordinate; vertices on a
+    non-periodic side keep their normal coordinate (straight boundaries).
+    Boundary sides get nbr_elem = the code and nbr_side = -1."""
+    left, right, bottom, top = bc
+    px = left == 0 and right == 0
+    py = bottom == 0 and top == 0
+    assert (left == 0) == (right == 0) and (bottom == 0) == (top == 0)
+    hx, hy = lx / nx, ly / ny
+    rng = np.random.default_rng(seed)
+    disp = rng.uniform(-jitter, jitter, size=(nx + 1, ny + 1, 2)) if jitter > 0 else np.zeros((nx + 1, ny + 1, 2))
+    disp[..., 0] *= hx
+    disp[..., 1] *= hy
+    if px:
+        disp[nx, :] = disp[0, :]
+    else:
+        disp[0, :, 0] = 0.0
+        disp[nx, :, 0] = 0.0
+    if py:
+        disp[:, ny] = disp[:, 0]
+    else:
+        disp[:, 0, 1] = 0.0
+        disp[:, ny, 1] = 0.0
+
+    def vert(i, j):
+        ii_, jj_ = (i % nx if px else i), (j % ny if py else j)
+        return np.stack([i * hx + disp[ii_, jj_, 0], j * hy + disp[ii_, jj_, 1]], axis=-1)
+
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    ii = ii.ravel()
+    jj = jj.ravel()
+    sq = jj * nx + ii
+    N = 2 * nx * ny
+    a, b = 2 * sq, 2 * sq + 1
+    vxy = np.empty((N, 3, 2))
+    vxy[a, 0], vxy[a, 1], vxy[a, 2] = vert(ii, jj), vert(ii + 1, jj), vert(ii + 1, jj + 1)
+    vxy[b, 0], vxy[b, 1], vxy[b, 2] = vert(ii, jj), vert(ii + 1, jj + 1), vert(ii, jj + 1)
+
+    def sqid(i, j):
+        return (j % ny) * nx + (i % nx)
+
+    nbr = np.empty((N, 3), dtype=np.int64)
+    nsd = np.empty((N, 3), dtype=np.int8)
+    nbr[a, 0], nsd[a, 0] = 2 * sqid(ii, jj - 1) + 1, 1
+    nbr[a, 1], nsd[a, 1] = 2 * sqid(ii + 1, jj) + 1, 2
+    nbr[a, 2], nsd[a, 2] = b, 0
+    nbr[b, 0], nsd[b, 0] = a, 2
+    nbr[b, 1], nsd[b, 1] = 2 * sqid(ii, jj + 1), 0
+    nbr[b, 2], nsd[b, 2] = 2 * sqid(ii - 1, jj), 1
+    if not py:
+        m = jj == 0
+        nbr[a[m], 0], nsd[a[m], 0] = bottom, -1
+        m = jj == ny - 1
+        nbr[b[m], 1], nsd[b[m], 1] = top, -1
+    if not px:
+        m = ii == nx - 1
+        nbr[a[m], 1], nsd[a[m], 1] = right, -1
+        m = ii == 0
+        nbr[b[m], 2], nsd[b[m], 2] = left, -1
+    name = f"box{nx}x{ny}_bc{left}{right}{bottom}{top}_j{jitter}_s{seed}"
+    return Mesh(vxy, nbr, nsd, max(lx, ly), name=name)
+
+
+def mirror_doubled_x(box: Mesh, lx: float) -> Mesh:
+    """The periodic mesh on [-lx, lx) x [0, ly) made of a box mesh whose
+    left and right sides (x = 0 and x = lx) are boundaries and its mirror
+    image about x = 0, with period 2 lx in x; elements 0..N-1 are the box's,
+    N..2N-1 their mirror images.  A mirrored element lists its vertices as
+    (v0, v2, v1) mirrored, so it stays counter-clockwise; its sides 0, 1, 2
+    are the mirrors of the original's sides 2, 1, 0.  Across x = 0 and
+    across the seam x = lx ~ -lx every boundary side meets the mirror image
+    of its own element."""
+    N = box.n_elem
+    side_map = np.array([2, 1, 0])  # mirrored element's side s <-> original side side_map[s]
+    vm = box.vxy[:, [0, 2, 1], :].copy()
+    vm[..., 0] *= -1.0
+    vxy = np.concatenate([box.vxy, vm])
+    nbr = np.empty((2 * N, 3), dtype=np.int64)
+    nsd = np.empty((2 * N, 3), dtype=np.int8)
+    inv = side_map  # involution: original side q <-> mirrored side inv[q]
+    for q in range(3):
+        nb = box.nbr_elem[:, q]
+        ns = box.nbr_side[:, q].astype(np.int64)
+        interior = nb >= 0
+        # original elements
+        nbr[:N, q] = np.where(interior, nb, np.arange(N) + N)
+        nsd[:N, q] = np.where(interior, ns, inv[q])
+        # mirrored elements: side inv[q] of element N+i mirrors side q of i
+        nbr[N:, inv[q]] = np.where(interior, nb + N, np.arange(N))
+        nsd[N:, inv[q]] = np.where(interior, inv[np.where(interior, ns, 0)], q)
+    assert (box.nbr_elem[box.nbr_elem < 0] != 0).all()
+    return Mesh(vxy, nbr, nsd, 2 * lx, name=box.name + "_mirrored")
+
+
 def delaunay_mesh(n_points: int, seed: int, length: float = 1.0, margin: float | None = None) -> Mesh:
     """Periodic Delaunay triangulation of n_points seeded uniform points in
     [0, length)^2.

@@ -37,7 +37,9 @@ def side_points(p):
 
 def centroid_bounds(orc, mesh, C):
     cen = orc.eval(C, np.array([1 / 3]), np.array([1 / 3]))[:, 0, :]  # [N, 4]
-    allc = np.concatenate([cen[:, None, :], cen[mesh.nbr_elem]], axis=1)
+    # a side on the domain boundary has no neighbour: count the element itself
+    nb = np.where(mesh.nbr_elem >= 0, mesh.nbr_elem, np.arange(mesh.n_elem)[:, None])
+    allc = np.concatenate([cen[:, None, :], cen[nb]], axis=1)
     return cen, allc.max(axis=1), allc.min(axis=1)
 
 
@@ -107,6 +109,14 @@ def test_limiter_properties_jump():
     C = orc.project(W.density_jump)
     L = orc.limit(C)
     assert check_limited(orc, mesh, C, L) > 0
+
+
+def test_limiter_properties_box():
+    # boundary sides contribute no neighbour to the bounds
+    mesh = W.box_mesh(12, 10, 1.0, 1.0, 0.2, 2, bc=(W.BC_WALL, W.BC_OUTFLOW, W.BC_STATE, W.BC_WALL))
+    orc = O.Oracle(mesh, 1)
+    C = rough_state(mesh.n_elem, 8)
+    assert check_limited(orc, mesh, C, orc.limit(C)) > 0
 
 
 def test_limiter_idempotent():

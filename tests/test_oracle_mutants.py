@@ -61,6 +61,12 @@ MUTANTS = {
     "rk4_last_stage_full_step": ("U[x] = C[x] + dt * L[x];\n        }\n        if (limit) orc_limit_bj(c, U);\n        orc_rhs(c, U, L);\n        for (size_t x = 0; x < len; ++x) C[x] = C[x] + dt * (K[x] + L[x]) / 6.0;",
                                  "U[x] = C[x] + 0.5 * dt * L[x];\n        }\n        if (limit) orc_limit_bj(c, U);\n        orc_rhs(c, U, L);\n        for (size_t x = 0; x < len; ++x) C[x] = C[x] + dt * (K[x] + L[x]) / 6.0;"),
     "rk2_weights": ("C[x] = 0.5 * C[x] + 0.5 * (U[x] + dt * L[x]);", "C[x] = 0.25 * C[x] + 0.75 * (U[x] + dt * L[x]);"),
+    "wall_half_reflection": ("UR[1] = UL[1] - 2.0 * mn * nx;", "UR[1] = UL[1] - mn * nx;"),
+    "outflow_takes_state": ("for (int m = 0; m < M; ++m) UR[m] = UL[m];\n    } else {",
+                            "for (int m = 0; m < M; ++m) UR[m] = c->bc_state[m];\n    } else {"),
+    "ghost_from_reversed_point": ("if (boundary) R_NAME(ghost)(c, nb, UL, nx, ny, UR);",
+                                  "if (boundary) { R_T Uc[M]; for (int m = 0; m < M; ++m) Uc[m] = UR[m]; "
+                                  "R_NAME(ghost)(c, nb, Uc, nx, ny, UR); }"),
 }
 
 
@@ -210,7 +216,26 @@ def pin_rk(lib):
     return bool(ok)
 
 
-PINS = [pin_rk, pin_limiter, pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
+def pin_boundary(lib):
+    from test_oracle_boundary import LX, mirror_data
+
+    box = W.box_mesh(4, 3, LX, 1.0, 0.2, 3, bc=(W.BC_WALL, W.BC_WALL, 0, 0))
+    dbl = W.mirror_doubled_x(box, LX)
+    ob, od = O.Oracle(box, 2, lib=lib), O.Oracle(dbl, 2, lib=lib)
+    Rb = ob.rhs(ob.project(mirror_data))
+    Rd = od.rhs(od.project(mirror_data))[: box.n_elem]
+    ok = np.abs(Rb - Rd).max() <= 1e-12 * np.abs(Rd).max()
+    bo = W.box_mesh(4, 3, 1.0, 1.0, 0.2, 5, bc=(W.BC_OUTFLOW,) * 4)
+    orc = O.Oracle(bo, 2, lib=lib)
+    orc.set_bc_state(np.array([9.0, 1.0, 1.0, 20.0]))
+    R = orc.rhs(orc.project(linear_state))
+    rs = np.array([[0.2, 0.3], [0.1, 0.4]])
+    ex = exact_dudt(*np.moveaxis(orc.map_points(rs[0], rs[1]), -1, 0))
+    ok &= np.abs(orc.eval(R, rs[0], rs[1]) - ex).max() < 1e-11 * np.abs(ex).max()
+    return bool(ok)
+
+
+PINS = [pin_boundary, pin_rk, pin_limiter, pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
 
 
 def run_pins(lib):
