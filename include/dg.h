@@ -102,14 +102,17 @@ int dg_mesh_validate(int p, int64_t n_elem, const double* vxy, const int64_t* nb
  *   vxy       host [n_elem][3][2] vertex coordinates, counter-clockwise so
  *             that det J of eq. (2dmap) is positive; periodic meshes give
  *             every element its own unwrapped coordinates;
- *   nbr_elem  host [n_elem][3]: element across local side q; a negative
- *             value is a boundary-condition code (not supported by this
- *             build: DG_EUNSUPPORTED);
- *   nbr_side  host [n_elem][3]: that neighbour's local side index;
+ *   nbr_elem  host [n_elem][3]: element across local side q, or a
+ *             negative boundary code for a side on the domain boundary
+ *             (DG_BC_WALL, DG_BC_OUTFLOW or DG_BC_STATE, see
+ *             dg_set_boundary_state; other negative values give
+ *             DG_EUNSUPPORTED);
+ *   nbr_side  host [n_elem][3]: that neighbour's local side index (ignored
+ *             on boundary sides);
  *   gamma     ratio of specific heats (1.4 for air);
  *   out       receives the handle.
- * Validation: det J > 0; neighbours point back; the two copies of every
- * edge are the same segment in opposite directions to within 1e-12 times
+ * Validation: det J > 0; interior neighbours point back; the two copies of every
+ * interior edge are the same segment in opposite directions to within 1e-12 times
  * the larger of its length and its vertices' coordinate magnitude (periodic
  * copies carry the rounding of shifted coordinates).
  * Validates first (see dg_mesh_validate), then builds the edge list (one
@@ -226,6 +229,27 @@ int dg_quad_weights(dg_mesh m, double* w_dev, void* stream);
  * Both give the same discrete operator (equal up to rounding). */
 enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1 };
 int dg_set_surface_mode(dg_mesh m, int mode);
+
+/* Domain boundaries (Section "Surface Integration Kernel": on a boundary
+ * edge the right-hand state is a ghost state that depends on the kind of
+ * boundary; Section "Mesh Connectivity": boundary sides carry a negative
+ * code in place of a neighbour).  At every Gauss point of a boundary side,
+ * with U the element's own trace and n the outward unit normal:
+ *   DG_BC_WALL (-1)     solid wall: density and energy kept, momentum
+ *                       mirrored, m_g = m - 2 (m . n) n;
+ *   DG_BC_OUTFLOW (-2)  the interior state itself (outflow / transmissive);
+ *   DG_BC_STATE (-3)    a constant prescribed state (inflow, far field,
+ *                       Dirichlet), set with dg_set_boundary_state from the
+ *                       host array U[4] = (rho, rho u, rho v, E); until then
+ *                       a gas at rest with rho = 1, p = 1 (gamma = 1.4).
+ * The local Lax-Friedrichs flux then takes the ghost as its right state.
+ * Boundaries are supported by the element-wise kernels (dg_rhs, dg_rk_step,
+ * dg_advance, both precisions, the limiter, which counts no neighbour on a
+ * boundary side); the edge-wise surface mode and the adjoint entry points
+ * return DG_EUNSUPPORTED on a mesh with boundaries.  dg_set_boundary_state
+ * is synchronous and returns DG_EINVAL for a non-physical state. */
+enum { DG_BC_WALL = -1, DG_BC_OUTFLOW = -2, DG_BC_STATE = -3 };
+int dg_set_boundary_state(dg_mesh m, const double* U);
 
 /* Time integrator of dg_rk_step and dg_advance: DG_RK_SSP3 (default; the
  * three-stage SSP scheme of dg_rk_step's comment), or the paper's classic

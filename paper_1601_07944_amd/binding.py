@@ -51,6 +51,7 @@ EXPORTS = [
     "dg_quad_weights",
     "dg_set_lanes_per_element",
     "dg_set_surface_mode",
+    "dg_set_boundary_state",
     "dg_set_integrator",
     "dg_set_limiter",
     "dg_limit",
@@ -117,6 +118,7 @@ def load(path: str = LIB_PATH):
     lib.dg_quad_weights.argtypes = [_vp, _vp, _vp]
     lib.dg_set_lanes_per_element.argtypes = [_vp, i32]
     lib.dg_set_surface_mode.argtypes = [_vp, i32]
+    lib.dg_set_boundary_state.argtypes = [_vp, _dp]
     lib.dg_set_integrator.argtypes = [_vp, i32]
     lib.dg_set_limiter.argtypes = [_vp, i32]
     lib.dg_limit.argtypes = [_vp, _vp, _vp]
@@ -297,6 +299,14 @@ class DGMesh:
 
     def set_surface_mode(self, mode: int):
         _check(self._lib.dg_set_surface_mode(self._h, int(mode)))
+
+    def set_boundary_state(self, U):
+        """Conserved state (rho, rho u, rho v, E) of boundary code DG_BC_STATE."""
+        import numpy as np
+
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (4,)
+        _check(self._lib.dg_set_boundary_state(self._h, U.ctypes.data_as(_dp)))
 
     RK_SSP3, RK2, RK4 = 0, 1, 2
 

@@ -108,10 +108,12 @@ int dg_mesh_validate(int p, int64_t n, const double* vxy, const int64_t* nbr, co
                         det);
         for (int q = 0; q < 3; ++q) {
             int64_t j = nbr[3 * i + q];
-            if (j < 0)
-                return fail(DG_EUNSUPPORTED, "element %lld side %d: boundary code %lld (only interior/periodic "
-                                             "connectivity is supported)",
-                            (long long)i, q, (long long)j);
+            if (j < 0) {
+                if (j < DG_BC_STATE)
+                    return fail(DG_EUNSUPPORTED, "element %lld side %d: unknown boundary code %lld", (long long)i, q,
+                                (long long)j);
+                continue;  // a domain boundary: nothing to match
+            }
             if (j >= n) return fail(DG_EMESH, "element %lld side %d: neighbour %lld out of range", (long long)i, q,
                                     (long long)j);
             int qn = nbs[3 * i + q];
@@ -205,6 +207,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         const int u = perm[i];
         const double* v = vxy + 6 * u;
         for (int q = 0; q < 3; ++q) {
+            if (nbr[3 * u + q] < 0) continue;  // domain boundary (element-wise path only)
             const int j = inv[nbr[3 * u + q]];
             const int qn = nbs[3 * u + q];
             if (j < i || (j == i && qn < q)) continue;
@@ -228,23 +231,35 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
 
     // per element side: neighbour (internal id), neighbour's side, own
     // outward unit normal and half length (from the element's own vertices)
-    std::vector<int> snb((size_t)npad * 3, 0), sside((size_t)npad, 0);
+    // A domain-boundary side gets the element itself as its "neighbour" (a
+    // harmless gather) and its kind in side_bc (4 bits per side: 0 interior,
+    // 1 wall, 2 outflow, 3 prescribed state).
+    std::vector<int> snb((size_t)npad * 3, 0), sside((size_t)npad, 0), sbc((size_t)npad, 0);
     std::vector<double> sg((size_t)npad * 9, 0.0);
+    bool has_bc = false;
     for (int i = 0; i < N; ++i) {
         const int u = perm[i];
         const double* v = vxy + 6 * u;
         const size_t b = (size_t)(i / 64) * 64;
-        int packed = 0;
+        int packed = 0, bcs = 0;
         for (int q = 0; q < 3; ++q) {
             double dx = v[2 * ((q + 1) % 3)] - v[2 * q], dy = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
             double len = std::sqrt(dx * dx + dy * dy);
-            snb[b * 3 + q * 64 + i % 64] = inv[nbr[3 * u + q]];
-            packed |= nbs[3 * u + q] << (2 * q);
+            const int64_t nq = nbr[3 * u + q];
+            if (nq < 0) {
+                has_bc = true;
+                bcs |= (int)(-nq) << (4 * q);
+                snb[b * 3 + q * 64 + i % 64] = i;
+            } else {
+                snb[b * 3 + q * 64 + i % 64] = inv[nq];
+                packed |= nbs[3 * u + q] << (2 * q);
+            }
             sg[b * 9 + (3 * q + 0) * 64 + i % 64] = dy / len;
             sg[b * 9 + (3 * q + 1) * 64 + i % 64] = -dx / len;
             sg[b * 9 + (3 * q + 2) * 64 + i % 64] = 0.5 * len;
         }
         sside[b + i % 64] = packed;
+        sbc[b + i % 64] = bcs;
     }
 
     dgh::TableLayout lay;
@@ -268,13 +283,15 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     };
     std::vector<float> tab32(tab.begin(), tab.end());
     void *d_tab32;
-    void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg, *d_snb, *d_sside, *d_sg;
+    void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg, *d_snb, *d_sside, *d_sg, *d_sbc, *d_bcs;
+    const double bc_state0[4] = {1.0, 0.0, 0.0, 2.5};  // until dg_set_boundary_state: gas at rest, p = 1
     if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(tab32.data(), tab32.size() * 4, &d_tab32)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
         (rc = upload(vtx.data(), vtx.size() * 8, &d_vtx)) || (rc = upload(perm.data(), perm.size() * 4, &d_perm)) ||
         (rc = upload(el.data(), el.size() * 4, &d_el)) || (rc = upload(er.data(), er.size() * 4, &d_er)) ||
         (rc = upload(sd.data(), sd.size() * 4, &d_sd)) || (rc = upload(eg.data(), eg.size() * 8, &d_eg)) ||
         (rc = upload(snb.data(), snb.size() * 4, &d_snb)) || (rc = upload(sside.data(), sside.size() * 4, &d_sside)) ||
-        (rc = upload(sg.data(), sg.size() * 8, &d_sg))) {
+        (rc = upload(sg.data(), sg.size() * 8, &d_sg)) || (rc = upload(sbc.data(), sbc.size() * 4, &d_sbc)) ||
+        (rc = upload(bc_state0, sizeof(bc_state0), &d_bcs))) {
         std::string msg = g_err;
         dg_mesh_destroy(m);
         return fail(rc, "%s", msg.c_str());
@@ -301,6 +318,9 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.side_nb = (const int*)d_snb;
     d.side_q = (const int*)d_sside;
     d.side_g = (const double*)d_sg;
+    d.side_bc = (const int*)d_sbc;
+    d.bc_state = (double*)d_bcs;
+    d.has_bc = has_bc;
     m->lay = lay;
 
     const size_t state = align256((size_t)npad * 4 * np * 8);
@@ -551,6 +571,7 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
 int dg_rhs_vjp(dg_mesh m, const double* C, const double* Rb, double* Cb, void* ws, void* stream)
 {
     if (!m || !C || !Rb || !Cb) return fail(DG_EINVAL, "null argument");
+    if (m->dev.has_bc) return fail(DG_EUNSUPPORTED, "the adjoint covers periodic meshes only");
     (void)ws;
     hipStream_t s = (hipStream_t)stream;
     timed(m, DG_KERNEL_VJP, s,
@@ -644,6 +665,7 @@ int dg_rk_step_vjp(dg_mesh m, const double* C, double dt, const double* dt_dev, 
     if (m->limiter != DG_LIMITER_NONE)
         return fail(DG_EUNSUPPORTED, "the limited step is not differentiable; switch the limiter off");
     if (m->integrator != DG_RK_SSP3) return fail(DG_EUNSUPPORTED, "the step adjoint is that of SSP-RK3");
+    if (m->dev.has_bc) return fail(DG_EUNSUPPORTED, "the adjoint covers periodic meshes only");
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
     char* w = (char*)ws;
@@ -686,6 +708,16 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes)
     return ok();
 }
 
+int dg_set_boundary_state(dg_mesh m, const double* U)
+{
+    if (!m || !U) return fail(DG_EINVAL, "null argument");
+    const double rho = U[0], p = (m->dev.gamma - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / rho);
+    if (!(rho > 0.0) || !(p > 0.0)) return fail(DG_EINVAL, "boundary state is not physical (rho = %g, p = %g)", rho, p);
+    hipError_t e = hipMemcpy(m->dev.bc_state, U, 4 * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "dg_set_boundary_state");
+    return ok();
+}
+
 int dg_set_integrator(dg_mesh m, int scheme)
 {
     if (!m) return fail(DG_EINVAL, "null mesh");
@@ -720,6 +752,8 @@ int dg_set_surface_mode(dg_mesh m, int mode)
     if (!m) return fail(DG_EINVAL, "null mesh");
     if (mode != DG_SURFACE_ELEMENTWISE && mode != DG_SURFACE_EDGEWISE)
         return fail(DG_EINVAL, "unknown surface mode %d", mode);
+    if (mode == DG_SURFACE_EDGEWISE && m->dev.has_bc)
+        return fail(DG_EUNSUPPORTED, "the edge-wise surface mode does not handle domain boundaries");
     m->surface = mode;
     return ok();
 }

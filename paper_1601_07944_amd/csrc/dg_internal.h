@@ -36,6 +36,11 @@ struct MeshDev {
     int npad = 0;      // padded to a multiple of 64
     int nedge = 0;
     bool lanes4 = false;  // fused kernels: 4 lanes per element instead of 1
+    // domain boundaries: per element 4 bits per side (0 interior, 1 wall,
+    // 2 outflow, 3 prescribed state), and the prescribed state (4 doubles)
+    const int* side_bc = nullptr;
+    double* bc_state = nullptr;
+    bool has_bc = false;
     double gamma = 1.4;
     const double* tab = nullptr;      // reference tables (TableLayout)
     const float* tab32 = nullptr;     // the same tables rounded to FP32 (mixed precision)

@@ -129,6 +129,26 @@ __device__ __forceinline__ void llf(T gamma, T gm1, const T UL[4], const T UR[4]
     for (int m = 0; m < 4; ++m) Fn[m] = T(0.5) * fma(-lam, UR[m] - UL[m], fL[m] + fR[m]);
 }
 
+// Ghost state across a domain boundary (Section "Surface Integration
+// Kernel": the right-hand state of a boundary edge is a ghost state set by
+// the kind of boundary), at the same point as UL, n the outward unit normal.
+// bc: 0 interior side (UR kept), 1 solid wall (density and energy kept,
+// momentum mirrored about the wall), 2 outflow (the interior state), 3 the
+// prescribed state G.  Written as selects, without branches: the kind varies
+// between the elements of a wavefront, and the stage kernels keep no
+// divergent control flow around their (heavily register-allocated) surface
+// loops.
+template <typename T>
+__device__ __forceinline__ void ghost_state(int bc, const T (&UL)[4], T nx, T ny, const T (&G)[4], T (&UR)[4])
+{
+    const bool keep = bc == 0, fixed = bc == 3;
+    const T s = bc == 1 ? T(2) * (UL[1] * nx + UL[2] * ny) : T(0);
+    UR[0] = keep ? UR[0] : (fixed ? G[0] : UL[0]);
+    UR[1] = keep ? UR[1] : (fixed ? G[1] : UL[1] - s * nx);
+    UR[2] = keep ? UR[2] : (fixed ? G[2] : UL[2] - s * ny);
+    UR[3] = keep ? UR[3] : (fixed ? G[3] : UL[3]);
+}
+
 // ---------------------------------------------------------------- traces
 template <int P>
 __device__ __forceinline__ void store_traces(const double (&c)[4][Ord<P>::NP], const double* __restrict__ tab,
@@ -398,14 +418,17 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk_grid)
 // stage-0 values are read through `out` itself, so every pointer can be
 // __restrict__ and the epilogue can stream (different (m, j) are provably
 // different addresses of one base).
-template <int P, int MODE, typename T>
+// BC: the mesh has domain-boundary sides (sbc, bcs read); periodic meshes
+// run the variant without them.
+template <int P, int MODE, typename T, bool BC>
 __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* __restrict__ C,
                                                  const double* __restrict__ U0, double* __restrict__ out,
                                                  const double* __restrict__ geo,
                                                  const int* __restrict__ snb, const int* __restrict__ sside,
                                                  const double* __restrict__ sgeo, const T* __restrict__ tab,
                                                  const double* __restrict__ tab64, double gamma, double dt,
-                                                 const double* __restrict__ dt_dev, StageGen gs)
+                                                 const double* __restrict__ dt_dev, StageGen gs,
+                                                 const int* __restrict__ sbc, const double* __restrict__ bcs)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
@@ -445,10 +468,15 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
 
     // surface integral, eq. (surface): the element's own three sides
     const int sides = sside[state_off(e, 1)];
+    const int bcv = BC ? sbc[state_off(e, 1)] : 0;
+    T G[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) G[m] = BC ? T(bcs[m]) : T(0);
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
         const int nb = snb[state_off(e, 3) + q * LANES];
         const int qn = (sides >> (2 * q)) & 3;
+        const int bc = (bcv >> (4 * q)) & 15;
         const int go = state_off(e, 9) + 3 * q * LANES;
         const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
         const double hl = sgeo[go + 2 * LANES];
@@ -483,6 +511,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
                 for (int j = 0; j < NP; ++j) u = fma(tl[j], c[m][j], u);
                 UL[m] = u;
             }
+            if constexpr (BC) ghost_state<T>(bc, UL, nx, ny, G, UR[k]);
             llf<T>(gam, gm1, UL, UR[k], nx, ny, F);
             const double w = -hl * tab64[O::GW + k];
             const double w0 = w * tab64[O::PHS + (q * NE + k) * NP];  // phi_0 is constant
@@ -642,19 +671,24 @@ constexpr int XQUAD = 4 * XROW;
 // element's geometry, and its quad's exchange slots.
 template <int P, typename T>
 struct Quad4 {
-    int e, m;
+    int e, m, bcv;  // bcv: the element's boundary kinds, 4 bits per side
     T gam, gm1, a00, a01, a10, a11;
+    T G[4];  // the prescribed boundary state
     double idet;
     Pair<T>* xr;
 };
 
-template <int P, typename T>
+template <int P, typename T, bool BC>
 __device__ __forceinline__ Quad4<P, T> quad4_setup(int e, int m, double gamma, const double* __restrict__ geo,
+                                                 const int* __restrict__ sbc, const double* __restrict__ bcs,
                                                  Pair<T>* xq)
 {
     Quad4<P, T> z;
     z.e = e;
     z.m = m;
+    z.bcv = BC ? sbc[state_off(e, 1)] : 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) z.G[v] = BC ? T(bcs[v]) : T(0);
     z.gam = T(gamma);
     z.gm1 = T(gamma - 1.0);
     const double* g = geo + state_off(e, 6);
@@ -672,12 +706,12 @@ __device__ __forceinline__ Quad4<P, T> quad4_setup(int e, int m, double gamma, c
 // and surface integral, eq. (surface), with the neighbours' coefficients
 // gathered from Cn.  acc[j] (j >= 1) in T, the mean mode acc0 in FP64.
 // phs: the side tables in LDS, sides' points reversed, rows of stride SS.
-template <int P, typename T>
+template <int P, typename T, bool BC>
 __device__ __forceinline__ void rhs_quad(const Quad4<P, T>& z, const T (&c)[Ord<P>::NP], const double* Cn,
                                          const int* __restrict__ snb, const int* __restrict__ sside,
                                          const double* __restrict__ sgeo, const T* __restrict__ tab,
-                                         const double* __restrict__ tab64, const T* phs,
-                                         T (&acc)[Ord<P>::NP], double& acc0)
+                                         const double* __restrict__ tab64, const T* phs, T (&acc)[Ord<P>::NP],
+                                         double& acc0)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
@@ -756,6 +790,7 @@ __device__ __forceinline__ void rhs_quad(const Quad4<P, T>& z, const T (&c)[Ord<
                 UL[v] = t.a;
                 UR[v] = t.b;
             }
+            if constexpr (BC) ghost_state<T>((z.bcv >> (4 * q)) & 15, UL, nx, ny, z.G, UR);
             llf<T>(z.gam, z.gm1, UL, UR, nx, ny, F);
             wave_sync();
 #pragma unroll
@@ -810,7 +845,7 @@ __device__ __forceinline__ void load_side_tables(const T* __restrict__ tab, T* p
 // and logical block 0 stores it to dt_store (and dt_hist); MODE 3 with
 // pout != nullptr writes the minimum over its 64 elements of the new
 // state's r_in / (|v| + c) to pout[logical block].
-template <int P, int MODE, typename T>
+template <int P, int MODE, typename T, bool BC>
 __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double* __restrict__ C,
                                                   const double* __restrict__ U0, double* __restrict__ out,
                                                   const double* __restrict__ geo, const int* __restrict__ snb,
@@ -819,7 +854,8 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
                                                   double gamma, double dt, const double* __restrict__ dt_dev,
                                                   const double* __restrict__ pin, int pin_count, double cfl,
                                                   double* __restrict__ dt_store, double* __restrict__ dt_hist,
-                                                  double* __restrict__ pout, StageGen gs)
+                                                  double* __restrict__ pout, StageGen gs,
+                                                  const int* __restrict__ sbc, const double* __restrict__ bcs)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NE = O::NE;
@@ -843,13 +879,13 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     if (e >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
     const bool real = e < n;
     const int so = state_off(e, 4 * NP) + m * NP * LANES;
-    const Quad4<P, T> z = quad4_setup<P, T>(e, m, gamma, geo, xq);
+    const Quad4<P, T> z = quad4_setup<P, T, BC>(e, m, gamma, geo, sbc, bcs, xq);
 
     T c[NP], acc[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) c[j] = T(C[so + j * LANES]);
     double acc0;
-    rhs_quad<P, T>(z, c, C, snb, sside, sgeo, tab, tab64, phs, acc, acc0);
+    rhs_quad<P, T, BC>(z, c, C, snb, sside, sgeo, tab, tab64, phs, acc, acc0);
 
     double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
     if constexpr (MODE == 1) {
@@ -916,7 +952,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
 // wavefronts to fill the GPU.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_limit_bj(int n, double* __restrict__ C, const int* __restrict__ snb,
-                                                    const double* __restrict__ tab)
+                                                    const int* __restrict__ sbc, const double* __restrict__ tab)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NE = O::NE;
@@ -931,11 +967,16 @@ __global__ __launch_bounds__(BLOCK) void k_limit_bj(int n, double* __restrict__ 
     for (int j = 0; j < NP; ++j) c[j] = C[so + j * LANES];
     const double ub = s2 * c[0];
     double umax = ub, umin = ub;
+    const int bcv = sbc[state_off(e, 1)];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
+        // a domain-boundary side has no neighbour (its snb entry is the
+        // element itself, which leaves the bounds unchanged)
         const double un = s2 * C[state_off(snb[state_off(e, 3) + q * LANES], 4 * NP) + m * NP * LANES];
-        umax = fmax(umax, un);
-        umin = fmin(umin, un);
+        if (((bcv >> (4 * q)) & 15) == 0) {
+            umax = fmax(umax, un);
+            umin = fmin(umin, un);
+        }
     }
     double a = 1.0;
 #pragma unroll
@@ -1478,55 +1519,42 @@ struct Launch {
                       double dt, const double* dt_dev, hipStream_t s, const FusedDt& fz = FusedDt(),
                       const StageGen& gs = StageGen())
     {
-        const int nb = (m.npad + BLOCK - 1) / BLOCK;
-        dim3 g((nb + 7) / 8 * 8);
-#define DG_STAGE(MODE, T, TAB)                                                                                  \
-    k_stage<P, MODE, T><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, TAB, \
-                                            m.tab, m.gamma, dt, dt_dev, gs)
+        if (mixed)
+            m.has_bc ? stage_t<float, true>(m, mode, m.tab32, C, U0, out, dt, dt_dev, s, fz, gs)
+                     : stage_t<float, false>(m, mode, m.tab32, C, U0, out, dt, dt_dev, s, fz, gs);
+        else
+            m.has_bc ? stage_t<double, true>(m, mode, m.tab, C, U0, out, dt, dt_dev, s, fz, gs)
+                     : stage_t<double, false>(m, mode, m.tab, C, U0, out, dt, dt_dev, s, fz, gs);
+    }
+    template <typename T, bool BC>
+    static void stage_t(const MeshDev& m, int mode, const T* tab, const double* C, const double* U0, double* out,
+                        double dt, const double* dt_dev, hipStream_t s, const FusedDt& fz, const StageGen& gs)
+    {
+        switch (mode) {
+        case 0: stage_m<0, T, BC>(m, tab, C, U0, out, dt, dt_dev, s, fz, gs); break;
+        case 1: stage_m<1, T, BC>(m, tab, C, U0, out, dt, dt_dev, s, fz, gs); break;
+        case 2: stage_m<2, T, BC>(m, tab, C, U0, out, dt, dt_dev, s, fz, gs); break;
+        case 3: stage_m<3, T, BC>(m, tab, C, U0, out, dt, dt_dev, s, fz, gs); break;
+        default: stage_m<4, T, BC>(m, tab, C, U0, out, dt, dt_dev, s, fz, gs); break;
+        }
+    }
+    template <int MODE, typename T, bool BC>
+    static void stage_m(const MeshDev& m, const T* tab, const double* C, const double* U0, double* out, double dt,
+                        const double* dt_dev, hipStream_t s, const FusedDt& fz, const StageGen& gs)
+    {
         if (m.lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
-#define DG_STAGE4(MODE, T, TAB)                                                                                  \
-    k_stage4<P, MODE, T><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q, m.side_g, TAB, \
-                                              m.tab, m.gamma, dt, dt_dev, fz.pin, fz.pin_count, fz.cfl,          \
-                                              fz.dt_store, fz.dt_hist, fz.pout, gs)
-            if (mixed) {
-                switch (mode) {
-                case 0: DG_STAGE4(0, float, m.tab32); break;
-                case 1: DG_STAGE4(1, float, m.tab32); break;
-                case 2: DG_STAGE4(2, float, m.tab32); break;
-                case 3: DG_STAGE4(3, float, m.tab32); break;
-                default: DG_STAGE4(4, float, m.tab32); break;
-                }
-            } else {
-                switch (mode) {
-                case 0: DG_STAGE4(0, double, m.tab); break;
-                case 1: DG_STAGE4(1, double, m.tab); break;
-                case 2: DG_STAGE4(2, double, m.tab); break;
-                case 3: DG_STAGE4(3, double, m.tab); break;
-                default: DG_STAGE4(4, double, m.tab); break;
-                }
-            }
-#undef DG_STAGE4
-            return;
-        }
-        if (mixed) {
-            switch (mode) {
-            case 0: DG_STAGE(0, float, m.tab32); break;
-            case 1: DG_STAGE(1, float, m.tab32); break;
-            case 2: DG_STAGE(2, float, m.tab32); break;
-            case 3: DG_STAGE(3, float, m.tab32); break;
-            default: DG_STAGE(4, float, m.tab32); break;
-            }
+            k_stage4<P, MODE, T, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q,
+                                                          m.side_g, tab, m.tab, m.gamma, dt, dt_dev, fz.pin,
+                                                          fz.pin_count, fz.cfl, fz.dt_store, fz.dt_hist, fz.pout, gs,
+                                                          m.side_bc, m.bc_state);
         } else {
-            switch (mode) {
-            case 0: DG_STAGE(0, double, m.tab); break;
-            case 1: DG_STAGE(1, double, m.tab); break;
-            case 2: DG_STAGE(2, double, m.tab); break;
-            case 3: DG_STAGE(3, double, m.tab); break;
-            default: DG_STAGE(4, double, m.tab); break;
-            }
+            const int nb = (m.npad + BLOCK - 1) / BLOCK;
+            dim3 g((nb + 7) / 8 * 8);
+            k_stage<P, MODE, T, BC><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q,
+                                                        m.side_g, tab, m.tab, m.gamma, dt, dt_dev, gs, m.side_bc,
+                                                        m.bc_state);
         }
-#undef DG_STAGE
     }
     static void stage_vjp(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X,
                           const double* Y, double* out, double dt, const double* dt_dev, hipStream_t s)

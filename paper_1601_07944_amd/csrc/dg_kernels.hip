@@ -109,7 +109,7 @@ void launch_dt_final(const double* partial, int count, double cfl, double* dt_de
 void launch_limit(const MeshDev& m, double* C, hipStream_t s)
 {
     // the limiter is defined for p = 1 only (the caller checks)
-    k_limit_bj<1><<<grid_for(4 * m.n), BLOCK, 0, s>>>(m.n, C, m.side_nb, m.tab);
+    k_limit_bj<1><<<grid_for(4 * m.n), BLOCK, 0, s>>>(m.n, C, m.side_nb, m.side_bc, m.tab);
 }
 
 void launch_pack(const MeshDev& m, const double* Cu, double* C, hipStream_t s)

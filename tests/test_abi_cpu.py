@@ -68,11 +68,18 @@ def test_validate_rejects_mismatched_edge():
     assert B.validate(1, v, m.nbr_elem, m.nbr_side) == -2
 
 
-def test_validate_rejects_boundary_codes():
+def test_validate_boundary_codes():
+    # box meshes with every kind of boundary are accepted; unknown codes are not
+    box = W.box_mesh(5, 4, 1.0, 1.0, 0.2, 1, bc=(W.BC_WALL, W.BC_OUTFLOW, W.BC_STATE, W.BC_WALL))
+    assert B.validate(2, box.vxy, box.nbr_elem, box.nbr_side) == 0
+    nb = box.nbr_elem.copy()
+    nb[nb == W.BC_OUTFLOW] = -4
+    assert B.validate(2, box.vxy, nb, box.nbr_side) == -4
+    # an interior side may not be half of a boundary: the neighbour must point back
     m = good_mesh()
     nb = m.nbr_elem.copy()
     nb[2, 1] = -1
-    assert B.validate(1, m.vxy, nb, m.nbr_side) == -4
+    assert B.validate(1, m.vxy, nb, m.nbr_side) == -2
 
 
 def test_validate_rejects_out_of_range():

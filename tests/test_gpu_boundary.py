@@ -1,0 +1,217 @@
+"""GPU domain boundaries (Section "Surface Integration Kernel": on a boundary
+edge the right-hand state is a ghost state set by the kind of boundary;
+Section "Mesh Connectivity": boundary sides carry a negative code) against
+the oracle's ghost states.
+
+Bars: 1e-11 relative L2 in FP64 (right-hand side, SSP-RK3, RK4 and limited
+steps); the mixed form within 3e-5 of the FP64 oracle for one right-hand
+side; dg_advance equals dg_max_dt + dg_rk_step bit for bit; walls on a box
+equal the mirror-doubled periodic mesh restricted to the box."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_07944_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+WALL, OUT, STATE = W.BC_WALL, W.BC_OUTFLOW, W.BC_STATE
+# (left, right, bottom, top); 0 on both sides of a direction = periodic
+BOXES = {
+    "walls": (WALL, WALL, WALL, WALL),
+    "outflow": (OUT, OUT, OUT, OUT),
+    "state": (STATE, STATE, STATE, STATE),
+    "channel": (STATE, OUT, WALL, WALL),
+    "x_walls_y_periodic": (WALL, WALL, 0, 0),
+}
+# a far-field state different from the interior, so the ghost matters
+U_FAR = W.primitive_to_conserved(np.array(1.2), np.array(0.4), np.array(-0.1), np.array(1.1)).reshape(4)
+
+
+def case(msg):
+    print(f"[gpu case] {msg}", file=sys.stderr, flush=True)
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def box(kind, nx=14, ny=12, seed=4):
+    # 14 x 12 x 2 = 336 elements: five full blocks of 64 and a ragged tail
+    return W.box_mesh(nx, ny, 1.0, 1.0, 0.2, seed, bc=BOXES[kind])
+
+
+def pair(mesh, p, lanes):
+    from paper_1601_07944_amd import binding as B
+
+    orc = O.Oracle(mesh, p)
+    dm = B.DGMesh.from_mesh(mesh, p)
+    dm.set_lanes(lanes)
+    orc.set_bc_state(U_FAR)
+    dm.set_boundary_state(U_FAR)
+    return orc, dm
+
+
+def flow(x, y):
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+    u = 0.3 + 0.1 * np.cos(2 * np.pi * y)
+    v = -0.2 + 0.1 * np.sin(2 * np.pi * x)
+    p = 1.0 + 0.1 * np.cos(2 * np.pi * (x + y))
+    return W.primitive_to_conserved(rho, u, v, p)
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("kind", sorted(BOXES))
+def test_rhs_matches_oracle(kind, p, lanes):
+    mesh = box(kind)
+    orc, dm = pair(mesh, p, lanes)
+    C = orc.project(flow) + 0.01 * W.random_state(mesh.n_elem, orc.np, seed=p)
+    case(f"dg_rhs box={kind} p={p} lanes={lanes}")
+    got = dm.unpack(dm.rhs(dm.pack(dev(C)))).cpu().numpy()
+    assert rel_l2(got, orc.rhs(C)) <= 1e-11
+
+
+@pytest.mark.parametrize("kind", ["walls", "channel"])
+@pytest.mark.parametrize("p", [1, 3, 5])
+def test_mixed_rhs_within_bound(kind, p):
+    mesh = box(kind)
+    orc, dm = pair(mesh, p, 0)
+    C = orc.project(flow)
+    case(f"dg_rhs DG_MIXED box={kind} p={p}")
+    got = dm.unpack(dm.rhs(dm.pack(dev(C)), prec=1)).cpu().numpy()
+    assert rel_l2(got, orc.rhs(C)) <= 3e-5
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("p", [1, 3, 4, 5])
+@pytest.mark.parametrize("kind", ["walls", "channel", "state"])
+def test_ssp3_steps_match_oracle(kind, p, lanes):
+    import torch
+
+    mesh = box(kind)
+    orc, dm = pair(mesh, p, lanes)
+    C0 = orc.project(flow)
+    dt, _ = orc.max_dt(C0, 0.3 / (2 * p + 1))
+    case(f"dg_rk_step x10 box={kind} p={p} lanes={lanes}")
+    Cg = dm.pack(dev(C0))
+    ref = C0
+    for _ in range(10):
+        dm.rk_step(Cg, dt)
+        ref = orc.rk3_step(ref, dt)
+    torch.cuda.synchronize()
+    assert rel_l2(dm.unpack(Cg).cpu().numpy(), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_advance_equals_max_dt_and_step(lanes):
+    import torch
+
+    mesh = box("channel")
+    orc, dm = pair(mesh, 3, lanes)
+    C0 = dm.pack(dev(orc.project(flow)))
+    cfl = 0.3 / 7
+    case(f"dg_advance x5 box=channel p=3 lanes={lanes}")
+    Ca = C0.clone()
+    dm.advance(Ca, 5, cfl)
+    Cs = C0.clone()
+    for _ in range(5):
+        dt_dev, _ = dm.max_dt(Cs, cfl)
+        dm.rk_step(Cs, dt_dev=dt_dev)
+    torch.cuda.synchronize()
+    assert torch.equal(Ca, Cs)
+
+
+def test_rk4_and_limited_steps_match_oracle():
+    import torch
+
+    mesh = box("channel")
+    orc, dm = pair(mesh, 2, 0)
+    C0 = orc.project(flow)
+    dt, _ = orc.max_dt(C0, 0.3 / 5)
+    dm.set_integrator(dm.RK4)
+    case("RK4 x8 box=channel p=2")
+    Cg = dm.pack(dev(C0))
+    ref = C0
+    for _ in range(8):
+        dm.rk_step(Cg, dt)
+        ref = orc.rk_step(ref, dt, "rk4")
+    torch.cuda.synchronize()
+    assert rel_l2(dm.unpack(Cg).cpu().numpy(), ref) <= 1e-11
+
+    orc1, dm1 = pair(mesh, 1, 0)
+    C1 = orc1.project(W.density_jump)
+    dt1, _ = orc1.max_dt(C1, 0.1)
+    dm1.set_limiter(dm1.LIMITER_BJ)
+    case("limited SSP-RK3 x10 box=channel p=1")
+    Cg = dm1.pack(dev(C1))
+    ref = C1
+    for _ in range(10):
+        dm1.rk_step(Cg, dt1)
+        ref = orc1.rk3_step(ref, dt1, limit=True)
+    torch.cuda.synchronize()
+    assert rel_l2(dm1.unpack(Cg).cpu().numpy(), ref) <= 1e-11
+    # the limiter alone, on a rough state, leaves boundary neighbours out like the oracle
+    R = W.random_state(mesh.n_elem, orc1.np, seed=3, amp=0.5)
+    got = dm1.unpack(dm1.limit(dm1.pack(dev(R)))).cpu().numpy()
+    assert rel_l2(got, orc1.limit(R)) <= 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_walls_equal_mirror_doubled_mesh(p):
+    from paper_1601_07944_amd import binding as B
+
+    mesh = W.box_mesh(8, 7, 1.0, 1.0, 0.2, 9, bc=(WALL, WALL, 0, 0))
+    dbl = W.mirror_doubled_x(mesh, 1.0)
+    ob = O.Oracle(mesh, p)
+    C = ob.project(lambda x, y: flow_even(x, y))
+    Cd = O.Oracle(dbl, p).project(lambda x, y: flow_even(x, y))
+    db, dd = B.DGMesh.from_mesh(mesh, p), B.DGMesh.from_mesh(dbl, p)
+    case(f"wall vs mirror-doubled periodic mesh p={p}")
+    Rb = db.unpack(db.rhs(db.pack(dev(C)))).cpu().numpy()
+    Rd = dd.unpack(dd.rhs(dd.pack(dev(Cd)))).cpu().numpy()[: mesh.n_elem]
+    assert np.abs(Rb - Rd).max() <= 1e-12 * np.abs(Rd).max()
+
+
+def flow_even(x, y):
+    # even in x for rho, rho v, E and odd for rho u, with period 2 in x
+    cx, sx = np.cos(np.pi * x), np.sin(np.pi * x)
+    rho = 1.0 + 0.2 * cx * np.sin(2 * np.pi * y)
+    u = 0.3 * sx
+    v = 0.2 * cx + 0.1 * np.sin(2 * np.pi * y)
+    p = 1.0 + 0.1 * cx * np.cos(2 * np.pi * y)
+    return W.primitive_to_conserved(rho, u, v, p)
+
+
+def test_boundary_error_paths():
+    from paper_1601_07944_amd import binding as B
+
+    mesh = box("walls", 6, 5)
+    dm = B.DGMesh.from_mesh(mesh, 2)
+    case("boundary error paths")
+    C = dm.pack(dev(W.random_state(mesh.n_elem, dm.np, seed=1)))
+    with pytest.raises(B.DGError) as e:
+        dm.set_surface_mode(dm.SURFACE_EDGEWISE)
+    assert e.value.code == -4
+    with pytest.raises(B.DGError) as e:
+        dm.rhs_vjp(C, C)
+    assert e.value.code == -4
+    with pytest.raises(B.DGError) as e:
+        dm.rk_step_vjp(C, C, 1e-3)
+    assert e.value.code == -4
+    with pytest.raises(B.DGError) as e:
+        dm.set_boundary_state([1.0, 0.0, 0.0, -1.0])
+    assert e.value.code == -1
+    with pytest.raises(B.DGError) as e:
+        dm.set_boundary_state([0.0, 0.0, 0.0, 1.0])
+    assert e.value.code == -1
+    # the mesh still works after the refusals
+    dm.rhs(C)

@@ -203,6 +203,28 @@ def test_rk_step_vortex_to_t1_small_config(surface):
     check_close(got, Co)
 
 
+@pytest.mark.parametrize("surface", sorted(SURFACE))
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_ssp3_steps_every_order(p, surface):
+    # ten SSP-RK3 steps of the vortex at every order and in every kernel
+    # organisation (the one-lane kernels run with register spills at p >= 4)
+    torch = torch_mod()
+    mesh = W.delaunay_mesh(650, 40 + p)
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.isentropic_vortex, center=(0.5, 0.5), period=1.0, beta=1.0)
+    dt, _ = orc.max_dt(C0, 0.3 / (2 * p + 1))
+    dm = gpu_mesh(mesh, p, SURFACE[surface])
+    case(f"dg_rk_step x10 p={p} surface={surface}")
+    Cg = dm.pack(to_dev(C0))
+    ref = C0
+    for _ in range(10):
+        dm.rk_step(Cg, dt)
+        ref = orc.rk3_step(ref, dt)
+    got = dm.unpack(Cg).cpu().numpy()
+    torch.cuda.synchronize()
+    check_close(got, ref)
+
+
 def test_rk_step_device_dt_matches_host_dt():
     # the step length read from device memory (dg_max_dt output) gives the
     # same result bit for bit as the host value

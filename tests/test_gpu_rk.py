@@ -40,7 +40,7 @@ def gpu_mesh(mesh, p, lanes=0):
 
 
 @pytest.mark.parametrize("lanes", [1, 4])
-@pytest.mark.parametrize("p", [1, 3, 5])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("scheme", sorted(SCHEMES))
 def test_rk_steps_match_oracle(scheme, p, lanes):
     import torch
