@@ -84,7 +84,7 @@ typedef struct {
     int n_edge_points;  /* p + 1 */
     int64_t n_elem;     /* elements */
     int64_t n_elem_pad; /* elements incl. padding (multiple of 64) */
-    int64_t n_edges;    /* edges (1.5 n_elem on a periodic mesh) */
+    int64_t n_edges;    /* edges: element pairs plus boundary sides (1.5 n_elem on a periodic mesh) */
     int64_t state_len;  /* doubles in one internal-layout state */
     int64_t ws_rhs;     /* workspace bytes for dg_rhs and dg_max_dt */
     int64_t ws_step;    /* workspace bytes for dg_rk_step and dg_rk_step_stages */
@@ -243,11 +243,13 @@ int dg_set_surface_mode(dg_mesh m, int mode);
  *                       host array U[4] = (rho, rho u, rho v, E); until then
  *                       a gas at rest with rho = 1, p = 1 (gamma = 1.4).
  * The local Lax-Friedrichs flux then takes the ghost as its right state.
- * Boundaries are supported by the element-wise kernels (dg_rhs, dg_rk_step,
- * dg_advance, both precisions, the limiter, which counts no neighbour on a
- * boundary side); the edge-wise surface mode and the adjoint entry points
- * return DG_EUNSUPPORTED on a mesh with boundaries.  dg_set_boundary_state
- * is synchronous and returns DG_EINVAL for a non-physical state. */
+ * Boundaries are supported by dg_rhs, dg_rk_step and dg_advance in both
+ * surface modes and both precisions, and by the limiter (which counts no
+ * neighbour on a boundary side).  In the edge-wise mode the boundary edges
+ * come first in the edge list, grouped by kind, so that whole wavefronts
+ * take the same branch.  The adjoint entry points return DG_EUNSUPPORTED on
+ * a mesh with boundaries.  dg_set_boundary_state is synchronous and returns
+ * DG_EINVAL for a non-physical state. */
 enum { DG_BC_WALL = -1, DG_BC_OUTFLOW = -2, DG_BC_STATE = -3 };
 int dg_set_boundary_state(dg_mesh m, const double* U);
 

@@ -199,26 +199,36 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         std::memcpy(&vtx[(size_t)i * 6], v, 6 * sizeof(double));
     }
 
-    // edges: one per element pair, left = lower internal id, sorted by left
+    // edges: boundary edges first, grouped by kind (Section "Surface
+    // Integration Kernel": whole wavefronts then take the same branch), with
+    // the boundary code in place of the right element; then one edge per
+    // element pair, left = lower internal id, sorted by left
     std::vector<int> el, er, sd;
     std::vector<double> egx, egy, egl;
     el.reserve(3 * N / 2 + 1);
+    auto add_edge = [&](int i, int j, int q, int qn) {
+        const double* v = vxy + 6 * perm[i];
+        double dx = v[2 * ((q + 1) % 3)] - v[2 * q], dy = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
+        double len = std::sqrt(dx * dx + dy * dy);
+        el.push_back(i);
+        er.push_back(j);
+        sd.push_back(q | (qn << 2));
+        egx.push_back(dy / len);
+        egy.push_back(-dx / len);
+        egl.push_back(0.5 * len);
+    };
+    for (int code = DG_BC_WALL; code >= DG_BC_STATE; --code)
+        for (int i = 0; i < N; ++i)
+            for (int q = 0; q < 3; ++q)
+                if (nbr[3 * perm[i] + q] == code) add_edge(i, code, q, 0);
     for (int i = 0; i < N; ++i) {
         const int u = perm[i];
-        const double* v = vxy + 6 * u;
         for (int q = 0; q < 3; ++q) {
-            if (nbr[3 * u + q] < 0) continue;  // domain boundary (element-wise path only)
+            if (nbr[3 * u + q] < 0) continue;
             const int j = inv[nbr[3 * u + q]];
             const int qn = nbs[3 * u + q];
             if (j < i || (j == i && qn < q)) continue;
-            double dx = v[2 * ((q + 1) % 3)] - v[2 * q], dy = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
-            double len = std::sqrt(dx * dx + dy * dy);
-            el.push_back(i);
-            er.push_back(j);
-            sd.push_back(q | (qn << 2));
-            egx.push_back(dy / len);
-            egy.push_back(-dx / len);
-            egl.push_back(0.5 * len);
+            add_edge(i, j, q, qn);
         }
     }
     const int nedge = (int)el.size();
@@ -752,8 +762,6 @@ int dg_set_surface_mode(dg_mesh m, int mode)
     if (!m) return fail(DG_EINVAL, "null mesh");
     if (mode != DG_SURFACE_ELEMENTWISE && mode != DG_SURFACE_EDGEWISE)
         return fail(DG_EINVAL, "unknown surface mode %d", mode);
-    if (mode == DG_SURFACE_EDGEWISE && m->dev.has_bc)
-        return fail(DG_EUNSUPPORTED, "the edge-wise surface mode does not handle domain boundaries");
     m->surface = mode;
     return ok();
 }

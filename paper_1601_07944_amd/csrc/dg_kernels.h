@@ -184,11 +184,16 @@ __global__ __launch_bounds__(BLOCK) void k_traces(int n, const double* __restric
 }
 
 // ---------------------------------------------------------------- edges
+// A boundary edge (right element = the negative boundary code; these edges
+// come first in the list, grouped by kind) takes the ghost state of its
+// left trace at the same point as the right state and writes the left slot
+// only.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_edge(int nedge, const int* __restrict__ el, const int* __restrict__ er,
                                                 const int* __restrict__ sd, const double* __restrict__ eg,
                                                 const double* __restrict__ T, double* __restrict__ S,
-                                                const double* __restrict__ tab, double gamma)
+                                                const double* __restrict__ tab, double gamma,
+                                                const double* __restrict__ bcs)
 {
     using O = Ord<P>;
     constexpr int NE = O::NE;
@@ -198,8 +203,23 @@ __global__ __launch_bounds__(BLOCK) void k_edge(int nedge, const int* __restrict
     const int ql = sides & 3, qr = (sides >> 2) & 3;
     const double nx = eg[i], ny = eg[nedge + i], hl = eg[2 * nedge + i];
     const int offl = state_off(l, 3 * NE * 4) + ql * NE * 4 * LANES;
-    const int offr = state_off(r, 3 * NE * 4) + qr * NE * 4 * LANES;
     const double gm1 = gamma - 1.0;
+    if (r < 0) {
+        const double G[4] = {bcs[0], bcs[1], bcs[2], bcs[3]};
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            double UL[4], UR[4], F[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) UR[m] = UL[m] = T[offl + (k * 4 + m) * LANES];
+            ghost_state<double>(-r, UL, nx, ny, G, UR);
+            llf<double>(gamma, gm1, UL, UR, nx, ny, F);
+            const double w = hl * tab[O::GW + k];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) S[offl + (k * 4 + m) * LANES] = -w * F[m];
+        }
+        return;
+    }
+    const int offr = state_off(r, 3 * NE * 4) + qr * NE * 4 * LANES;
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
         const int kr = NE - 1 - k;
@@ -1498,7 +1518,7 @@ struct Launch {
     static void edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s)
     {
         k_edge<P><<<grid_for(m.nedge), BLOCK, 0, s>>>(m.nedge, m.edge_l, m.edge_r, m.edge_sd, m.edge_g, T, S, m.tab,
-                                                      m.gamma);
+                                                      m.gamma, m.bc_state);
     }
     static void element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
                         double dt, const double* dt_dev, double* Tn, hipStream_t s)
