@@ -462,6 +462,16 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     ms_step_edge = e0.elapsed_time(e1) / args.steps
+
+    # coloured edges: one launch per colour, lifts added in place
+    dm.set_surface_mode(dm.SURFACE_COLOURED)
+    steps_prec(C, B.DG_FP64, 5)
+    torch.cuda.synchronize()
+    e0.record()
+    steps_prec(C, B.DG_FP64, args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step_col = e0.elapsed_time(e1) / args.steps
     dm.set_surface_mode(dm.SURFACE_ELEMENTWISE)
 
     limiter = limiter_overhead(args.steps)
@@ -499,6 +509,8 @@ def main():
         "kernels": kernels,
         "ms_per_step_with_kernel_events": ms_step_events,
         "surface_edgewise": {"ms_per_step": ms_step_edge, "value": dof * 3 / (ms_step_edge * 1e-3)},
+        "surface_coloured": {"ms_per_step": ms_step_col, "value": dof * 3 / (ms_step_col * 1e-3),
+                             "colours": int(dm.info.n_colours)},
         "lanes_per_element": {"headline": 4 if auto4 else 1, "alternative": lanes_alt,
                               "alternative_ms_per_step": ms_step_alt},
         "wall_s_timed_region": wall,

@@ -89,6 +89,7 @@ typedef struct {
     int64_t ws_rhs;     /* workspace bytes for dg_rhs and dg_max_dt */
     int64_t ws_step;    /* workspace bytes for dg_rk_step and dg_rk_step_stages */
     int64_t ws_vjp;     /* workspace bytes for dg_rk_step_vjp */
+    int64_t n_colours;  /* colours of the edge colouring (DG_SURFACE_COLOURED) */
 } dg_info;
 
 /* Checks a mesh without touching the GPU (no HIP call).  Arguments as for
@@ -225,9 +226,18 @@ int dg_quad_weights(dg_mesh m, double* w_dev, void* stream);
  *   DG_SURFACE_EDGEWISE: the paper's organisation: one work-item per edge
  *     evaluates the flux once and stores it for both elements (per-side
  *     slots, no atomics), then an element kernel combines; three kernels
- *     per right-hand side.
- * Both give the same discrete operator (equal up to rounding). */
-enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1 };
+ *     per right-hand side;
+ *   DG_SURFACE_COLOURED: the alternative the paper proposes for its
+ *     edge-wise kernel (Section "Conclusion"): the edges are coloured so
+ *     that no two edges of one colour share an element (greedy, at most
+ *     five colours, dg_info.n_colours), and one launch per colour lets each
+ *     edge add its lifted flux straight into both elements' accumulators,
+ *     with no slots and no atomics; then the element kernel adds the
+ *     volume integral and finishes the stage.
+ * All give the same discrete operator (equal up to rounding).  The two
+ * edge-based modes run in FP64 only, without the limiter and with SSP-RK3
+ * only (DG_EUNSUPPORTED otherwise). */
+enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1, DG_SURFACE_COLOURED = 2 };
 int dg_set_surface_mode(dg_mesh m, int mode);
 
 /* Domain boundaries (Section "Surface Integration Kernel": on a boundary

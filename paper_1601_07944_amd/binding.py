@@ -81,6 +81,7 @@ class dg_info(ctypes.Structure):
         ("ws_rhs", ctypes.c_int64),
         ("ws_step", ctypes.c_int64),
         ("ws_vjp", ctypes.c_int64),
+        ("n_colours", ctypes.c_int64),
     ]
 
 
@@ -292,6 +293,7 @@ class DGMesh:
     KERNELS = ("traces", "edge", "element", "dt", "stage", "vjp", "limit")
     SURFACE_ELEMENTWISE = 0
     SURFACE_EDGEWISE = 1
+    SURFACE_COLOURED = 2
 
     def set_lanes(self, lanes: int):
         """Work-items per element in the element-wise kernels: 0 (auto), 1 or 4."""

@@ -232,11 +232,44 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         }
     }
     const int nedge = (int)el.size();
-    std::vector<double> eg(3 * (size_t)nedge);
+
+    // greedy edge colouring in list order (lowest colour free at both
+    // elements; at most 5 colours since an edge meets at most 4 others),
+    // and a second copy of the edge arrays stably sorted by colour (within a
+    // colour the boundary edges stay first, grouped by kind, and the
+    // interior edges sorted by left element); the slot path keeps the list
+    // order
+    std::vector<unsigned char> used((size_t)N, 0), colour((size_t)nedge);
+    int ncolour = 0;
+    for (int i = 0; i < nedge; ++i) {
+        const unsigned busy = used[el[i]] | (er[i] >= 0 ? used[er[i]] : 0u);
+        int c = 0;
+        while (busy & (1u << c)) ++c;
+        colour[i] = (unsigned char)c;
+        used[el[i]] |= (unsigned char)(1u << c);
+        if (er[i] >= 0) used[er[i]] |= (unsigned char)(1u << c);
+        ncolour = std::max(ncolour, c + 1);
+    }
+    if (ncolour > dgk::MeshDev::MAX_COLOURS) return fail(DG_EMESH, "edge colouring needs %d colours", ncolour);
+    std::vector<int> order(nedge);
+    for (int i = 0; i < nedge; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return colour[a] < colour[b]; });
+    int colour_off[dgk::MeshDev::MAX_COLOURS + 1] = {};
+    for (int i = 0; i < nedge; ++i) ++colour_off[colour[i] + 1];
+    for (int c = 0; c < ncolour; ++c) colour_off[c + 1] += colour_off[c];
+    std::vector<int> ecol((size_t)3 * nedge);  // [3][nedge]: left, right, sides in colour order
+    std::vector<double> eg(3 * (size_t)nedge), egc(3 * (size_t)nedge);
     for (int i = 0; i < nedge; ++i) {
         eg[i] = egx[i];
         eg[nedge + i] = egy[i];
         eg[2 * (size_t)nedge + i] = egl[i];
+        const int o = order[i];
+        ecol[i] = el[o];
+        ecol[nedge + i] = er[o];
+        ecol[2 * (size_t)nedge + i] = sd[o];
+        egc[i] = egx[o];
+        egc[nedge + i] = egy[o];
+        egc[2 * (size_t)nedge + i] = egl[o];
     }
 
     // per element side: neighbour (internal id), neighbour's side, own
@@ -294,6 +327,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     std::vector<float> tab32(tab.begin(), tab.end());
     void *d_tab32;
     void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg, *d_snb, *d_sside, *d_sg, *d_sbc, *d_bcs;
+    void *d_ecol, *d_egc;
     const double bc_state0[4] = {1.0, 0.0, 0.0, 2.5};  // until dg_set_boundary_state: gas at rest, p = 1
     if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(tab32.data(), tab32.size() * 4, &d_tab32)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
         (rc = upload(vtx.data(), vtx.size() * 8, &d_vtx)) || (rc = upload(perm.data(), perm.size() * 4, &d_perm)) ||
@@ -301,7 +335,8 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         (rc = upload(sd.data(), sd.size() * 4, &d_sd)) || (rc = upload(eg.data(), eg.size() * 8, &d_eg)) ||
         (rc = upload(snb.data(), snb.size() * 4, &d_snb)) || (rc = upload(sside.data(), sside.size() * 4, &d_sside)) ||
         (rc = upload(sg.data(), sg.size() * 8, &d_sg)) || (rc = upload(sbc.data(), sbc.size() * 4, &d_sbc)) ||
-        (rc = upload(bc_state0, sizeof(bc_state0), &d_bcs))) {
+        (rc = upload(bc_state0, sizeof(bc_state0), &d_bcs)) || (rc = upload(ecol.data(), ecol.size() * 4, &d_ecol)) ||
+        (rc = upload(egc.data(), egc.size() * 8, &d_egc))) {
         std::string msg = g_err;
         dg_mesh_destroy(m);
         return fail(rc, "%s", msg.c_str());
@@ -314,6 +349,10 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.n = N;
     d.npad = npad;
     d.nedge = nedge;
+    d.ncolour = ncolour;
+    d.ecol = (const int*)d_ecol;
+    d.edge_gc = (const double*)d_egc;
+    for (int c = 0; c <= ncolour; ++c) d.colour_off[c] = colour_off[c];
     d.gamma = gamma;
     d.lanes4 = N <= DG_LANES4_MAX_ELEMENTS || p >= 4;
     d.tab = (const double*)d_tab;
@@ -336,17 +375,20 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     const size_t state = align256((size_t)npad * 4 * np * 8);
     const size_t trace = align256((size_t)npad * 3 * ne * 4 * 8);
     const size_t part = align256((size_t)dgk::dt_partials(d) * 8);
+    // S: the side slots of the edge-wise mode, or the accumulator state of
+    // the coloured mode
+    const size_t slot = std::max(trace, state);
     m->off_T0 = 0;
     m->off_S = trace;
-    m->off_part = 2 * trace;
-    m->ws_rhs = (int64_t)(2 * trace + part);
-    m->off_T1 = 2 * trace + part;
-    m->off_u1 = 3 * trace + part;
-    m->off_u2 = 3 * trace + part + state;
-    m->off_part4 = 3 * trace + part + 2 * state;
+    m->off_part = trace + slot;
+    m->ws_rhs = (int64_t)(trace + slot + part);
+    m->off_T1 = trace + slot + part;
+    m->off_u1 = 2 * trace + slot + part;
+    m->off_u2 = 2 * trace + slot + part + state;
+    m->off_part4 = 2 * trace + slot + part + 2 * state;
     const size_t part4 = align256((size_t)dgk::stage4_partials(d) * 8);
-    m->off_acc = 3 * trace + part + 2 * state + part4;
-    m->ws_step = (int64_t)(3 * trace + part + 3 * state + part4);
+    m->off_acc = 2 * trace + slot + part + 2 * state + part4;
+    m->ws_step = (int64_t)(2 * trace + slot + part + 3 * state + part4);
     m->state_bytes = state;
     m->ws_vjp = (int64_t)(4 * state);
     *out = m;
@@ -377,6 +419,7 @@ int dg_mesh_info(dg_mesh m, dg_info* out)
     out->n_elem = m->dev.n;
     out->n_elem_pad = m->dev.npad;
     out->n_edges = m->dev.nedge;
+    out->n_colours = m->dev.ncolour;
     out->state_len = (int64_t)m->dev.npad * 4 * m->dev.np;
     out->ws_rhs = m->ws_rhs;
     out->ws_step = m->ws_step;
@@ -467,6 +510,13 @@ int dg_rhs(dg_mesh m, const double* C, double* R, dg_precision prec, void* ws, v
     if (m->surface == DG_SURFACE_ELEMENTWISE) {
         const bool mixed = prec == DG_MIXED;
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(m->dev, 0, mixed, C, nullptr, R, 0.0, nullptr, s); });
+        return check_launch("dg_rhs");
+    }
+    if (m->surface == DG_SURFACE_COLOURED) {
+        timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s, S); });
+        timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_lift(m->dev, T, S, s); });
+        timed(m, DG_KERNEL_ELEMENT, s,
+              [&] { dgk::launch_element(m->dev, 0, C, nullptr, R, nullptr, 0.0, nullptr, nullptr, s, S); });
         return check_launch("dg_rhs");
     }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s); });
@@ -566,6 +616,16 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
         limit_stage(m, u2, s);
         timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, mx, u2, nullptr, C, dt, dt_dev, s); });
         limit_stage(m, C, s);
+        return check_launch("dg_rk_step");
+    }
+    if (m->surface == DG_SURFACE_COLOURED) {
+        timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s, S); });
+        timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_lift(d, T0, S, s); });
+        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 1, C, nullptr, u1, nullptr, dt, dt_dev, T1, s, S); });
+        timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_lift(d, T1, S, s); });
+        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 2, u1, C, u2, nullptr, dt, dt_dev, T0, s, S); });
+        timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_lift(d, T0, S, s); });
+        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 3, u2, C, C, nullptr, dt, dt_dev, nullptr, s, S); });
         return check_launch("dg_rk_step");
     }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s); });
@@ -760,7 +820,7 @@ int dg_limit(dg_mesh m, double* C, void* stream)
 int dg_set_surface_mode(dg_mesh m, int mode)
 {
     if (!m) return fail(DG_EINVAL, "null mesh");
-    if (mode != DG_SURFACE_ELEMENTWISE && mode != DG_SURFACE_EDGEWISE)
+    if (mode != DG_SURFACE_ELEMENTWISE && mode != DG_SURFACE_EDGEWISE && mode != DG_SURFACE_COLOURED)
         return fail(DG_EINVAL, "unknown surface mode %d", mode);
     m->surface = mode;
     return ok();

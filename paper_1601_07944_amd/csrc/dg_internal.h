@@ -51,6 +51,13 @@ struct MeshDev {
     const int* edge_r = nullptr;      // [nedge] right element
     const int* edge_sd = nullptr;     // [nedge] side_l | side_r << 2
     const double* edge_g = nullptr;   // SoA [3][nedge]: unit normal (left -> right) x, y; half length
+    // edge colouring: edges sorted by colour, colour c = [colour_off[c],
+    // colour_off[c+1]); no two edges of one colour share an element
+    static constexpr int MAX_COLOURS = 8;
+    int ncolour = 0;
+    int colour_off[MAX_COLOURS + 1] = {};
+    const int* ecol = nullptr;        // [3][nedge] left, right, sides (as edge_l/r/sd) in colour order
+    const double* edge_gc = nullptr;  // [3][nedge] as edge_g, in colour order
     // per element side (element-wise surface integration), block-major:
     const int* side_nb = nullptr;     // [blk][3][64] neighbour across side q (internal id)
     const int* side_q = nullptr;      // [blk][64] neighbour's sides, 2 bits per side
@@ -71,12 +78,19 @@ struct FusedDt {
 };
 
 // Launchers (dg_kernels.hip).  All asynchronous on `s`.
-void launch_traces(const MeshDev& m, const double* C, double* T, hipStream_t s);
+// Rz (optional): an accumulator state zeroed for the elements' own slots
+void launch_traces(const MeshDev& m, const double* C, double* T, hipStream_t s, double* Rz = nullptr);
+// coloured edges: one launch per colour, each edge lifting its flux
+// straight into both elements' accumulators R (race-free within a colour)
+void launch_edge_lift(const MeshDev& m, const double* T, double* R, hipStream_t s);
 void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s);
 // mode 0: R = L(C);   mode 1..3: SSP-RK3 stage (out = stage result);
 // when Tnext != nullptr the traces of `out` are written to it.
+// Racc (optional, coloured edges): take the surface integral from the
+// accumulator instead of lifting the side slots S, and zero it again when
+// Tnext is set (the next stage accumulates into it)
 void launch_element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
-                    double dt, const double* dt_dev, double* Tnext, hipStream_t s);
+                    double dt, const double* dt_dev, double* Tnext, hipStream_t s, double* Racc = nullptr);
 // fused right-hand side / SSP-RK3 stage (element-wise surface integral);
 // mode as for launch_element, except that mode 3 updates `out` in place
 // (it is the stage-0 state) and U0 must be nullptr

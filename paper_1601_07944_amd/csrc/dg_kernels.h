@@ -169,11 +169,15 @@ __device__ __forceinline__ void store_traces(const double (&c)[4][Ord<P>::NP], c
 
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_traces(int n, const double* __restrict__ C, double* __restrict__ T,
-                                                  const double* __restrict__ tab)
+                                                  const double* __restrict__ tab, double* __restrict__ Rz)
 {
     using O = Ord<P>;
     const int e = blockIdx.x * BLOCK + threadIdx.x;
     if (e >= n) return;
+    if (Rz) {
+#pragma unroll
+        for (int x = 0; x < 4 * O::NP; ++x) Rz[state_off(e, 4 * O::NP) + x * LANES] = 0.0;
+    }
     const double* c0 = C + state_off(e, 4 * O::NP);
     double c[4][O::NP];
 #pragma unroll
@@ -239,15 +243,86 @@ __global__ __launch_bounds__(BLOCK) void k_edge(int nedge, const int* __restrict
     }
 }
 
+// Edge colouring (the paper's suggested alternative to per-side
+// temporaries): the edges of one colour share no element, so one launch per
+// colour lets every edge evaluate its flux once and add its lift straight
+// into both elements' accumulators R[blk][m][j][lane] (before 1/det J),
+// without atomics and without a slot buffer.  The side tables sit in LDS
+// (the side differs per edge).
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_edge_lift(int e0, int e1, int nedge, const int* __restrict__ el,
+                                                     const int* __restrict__ er, const int* __restrict__ sd,
+                                                     const double* __restrict__ eg, const double* __restrict__ T,
+                                                     double* __restrict__ R, const double* __restrict__ tab,
+                                                     double gamma, const double* __restrict__ bcs)
+{
+    using O = Ord<P>;
+    constexpr int NE = O::NE, NP = O::NP;
+    __shared__ double phs[3 * NE * NP];
+    for (int x = threadIdx.x; x < 3 * NE * NP; x += BLOCK) phs[x] = tab[O::PHS + x];
+    __syncthreads();
+    const int i = e0 + blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= e1) return;
+    const int l = el[i], r = er[i], sides = sd[i];
+    const int ql = sides & 3, qr = (sides >> 2) & 3;
+    const double nx = eg[i], ny = eg[nedge + i], hl = eg[2 * nedge + i];
+    const int offl = state_off(l, 3 * NE * 4) + ql * NE * 4 * LANES;
+    const int offr = r >= 0 ? state_off(r, 3 * NE * 4) + qr * NE * 4 * LANES : 0;
+    const double gm1 = gamma - 1.0;
+    const double G[4] = {bcs[0], bcs[1], bcs[2], bcs[3]};
+    double WF[NE][4];  // l * omega_k * Fn at the left element's points
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        double UL[4], UR[4], F[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) UR[m] = UL[m] = T[offl + (k * 4 + m) * LANES];
+        if (r >= 0) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) UR[m] = T[offr + ((NE - 1 - k) * 4 + m) * LANES];
+        } else {
+            ghost_state<double>(-r, UL, nx, ny, G, UR);
+        }
+        llf<double>(gamma, gm1, UL, UR, nx, ny, F);
+        const double w = hl * tab[O::GW + k];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) WF[k][m] = w * F[m];
+    }
+    const double* tl = phs + ql * NE * NP;
+    const double* tr = phs + qr * NE * NP;
+    const int sl = state_off(l, 4 * NP), sr = r >= 0 ? state_off(r, 4 * NP) : 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < NE; ++k) a = fma(tl[k * NP + j], WF[k][m], a);
+            R[sl + (m * NP + j) * LANES] -= a;
+        }
+    if (r < 0) return;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < NE; ++k) a = fma(tr[(NE - 1 - k) * NP + j], WF[k][m], a);
+            R[sr + (m * NP + j) * LANES] += a;
+        }
+}
+
 // ---------------------------------------------------------------- elements
 // The grid covers the padded element count: padding lanes write zeros, so
 // every state this kernel produces has a defined (zero) padding.
-template <int P, int MODE, bool TRACE>
+// RACC: the surface integral is already in Racc (coloured edges): start the
+// accumulators from it instead of lifting the side slots S, and zero it
+// again when the next stage's traces are written.
+template <int P, int MODE, bool TRACE, bool RACC>
 __global__ __launch_bounds__(BLOCK) void k_element(int n, int npad, const double* __restrict__ C, const double* U0,
                                                    double* out, const double* __restrict__ S,
                                                    const double* __restrict__ geo, const double* __restrict__ tab,
                                                    double gm1, double dt, const double* __restrict__ dt_dev,
-                                                   double* __restrict__ Tn)
+                                                   double* __restrict__ Tn, double* __restrict__ Racc)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
@@ -272,7 +347,11 @@ __global__ __launch_bounds__(BLOCK) void k_element(int n, int npad, const double
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int j = 0; j < NP; ++j) acc[m][j] = 0.0;
+        for (int j = 0; j < NP; ++j) acc[m][j] = RACC ? Racc[so + (m * NP + j) * LANES] : 0.0;
+    if constexpr (RACC && TRACE) {
+#pragma unroll
+        for (int x = 0; x < 4 * NP; ++x) Racc[so + x * LANES] = 0.0;
+    }
 
     // volume integral: sum_k w_k grad phi_j(r_k) . (adj(J) F(U(r_k)));
     // the point loop stays rolled so only one point's table rows are live
@@ -300,7 +379,7 @@ __global__ __launch_bounds__(BLOCK) void k_element(int n, int npad, const double
     // surface integral: lift the three side slots (already l * omega_k * Fn)
     const int to = state_off(e, 3 * NE * 4);
 #pragma unroll 1
-    for (int qk = 0; qk < 3 * NE; ++qk) {
+    for (int qk = 0; qk < (RACC ? 0 : 3 * NE); ++qk) {
         double sv[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) sv[m] = S[to + (qk * 4 + m) * LANES];
@@ -1511,9 +1590,19 @@ static inline dim3 grid_for(int n) { return dim3((n + BLOCK - 1) / BLOCK); }
 
 template <int P>
 struct Launch {
-    static void traces(const MeshDev& m, const double* C, double* T, hipStream_t s)
+    static void traces(const MeshDev& m, const double* C, double* T, hipStream_t s, double* Rz)
     {
-        k_traces<P><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, C, T, m.tab);
+        k_traces<P><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, C, T, m.tab, Rz);
+    }
+    static void edge_lift(const MeshDev& m, const double* T, double* R, hipStream_t s)
+    {
+        for (int c = 0; c < m.ncolour; ++c) {
+            const int e0 = m.colour_off[c], e1 = m.colour_off[c + 1];
+            if (e1 > e0)
+                k_edge_lift<P><<<grid_for(e1 - e0), BLOCK, 0, s>>>(e0, e1, m.nedge, m.ecol, m.ecol + m.nedge,
+                                                                   m.ecol + 2 * m.nedge, m.edge_gc, T, R, m.tab,
+                                                                   m.gamma, m.bc_state);
+        }
     }
     static void edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s)
     {
@@ -1521,12 +1610,22 @@ struct Launch {
                                                       m.gamma, m.bc_state);
     }
     static void element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
-                        double dt, const double* dt_dev, double* Tn, hipStream_t s)
+                        double dt, const double* dt_dev, double* Tn, hipStream_t s, double* Racc)
+    {
+        if (Racc)
+            element_t<true>(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc);
+        else
+            element_t<false>(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc);
+    }
+    template <bool RACC>
+    static void element_t(const MeshDev& m, int mode, const double* C, const double* U0, double* out,
+                          const double* S, double dt, const double* dt_dev, double* Tn, hipStream_t s, double* Racc)
     {
         const double gm1 = m.gamma - 1.0;
         dim3 g = grid_for(m.npad);
-#define DG_ELEM(MODE, TR) \
-    k_element<P, MODE, TR><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, S, m.geo, m.tab, gm1, dt, dt_dev, Tn)
+#define DG_ELEM(MODE, TR)                                                                                     \
+    k_element<P, MODE, TR, RACC><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, S, m.geo, m.tab, gm1, dt, dt_dev, \
+                                                     Tn, Racc)
         switch (mode) {
         case 0: DG_ELEM(0, false); break;
         case 1: if (Tn) DG_ELEM(1, true); else DG_ELEM(1, false); break;

@@ -50,7 +50,15 @@ __global__ __launch_bounds__(BLOCK) void k_unpack(int n, int np, const int* __re
     default: Launch<5>::CALL; break;               \
     }
 
-void launch_traces(const MeshDev& m, const double* C, double* T, hipStream_t s) { DG_DISPATCH_P(m.p, traces(m, C, T, s)); }
+void launch_traces(const MeshDev& m, const double* C, double* T, hipStream_t s, double* Rz)
+{
+    DG_DISPATCH_P(m.p, traces(m, C, T, s, Rz));
+}
+
+void launch_edge_lift(const MeshDev& m, const double* T, double* R, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, edge_lift(m, T, R, s));
+}
 
 void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s)
 {
@@ -58,9 +66,9 @@ void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t 
 }
 
 void launch_element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
-                    double dt, const double* dt_dev, double* Tn, hipStream_t s)
+                    double dt, const double* dt_dev, double* Tn, hipStream_t s, double* Racc)
 {
-    DG_DISPATCH_P(m.p, element(m, mode, C, U0, out, S, dt, dt_dev, Tn, s));
+    DG_DISPATCH_P(m.p, element(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc));
 }
 
 void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out, double dt,

@@ -80,18 +80,20 @@ def test_rhs_matches_oracle(kind, p, lanes):
     assert rel_l2(got, orc.rhs(C)) <= 1e-11
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("kind", sorted(BOXES))
-def test_edgewise_rhs_and_steps_match_oracle(kind, p):
-    # the paper's organisation: boundary edges first in the edge list, one
-    # flux per edge, ghost state on boundary edges
+def test_edge_based_rhs_and_steps_match_oracle(kind, p, mode):
+    # the paper's organisation (1: boundary edges first in the edge list,
+    # one flux per edge into side slots) and coloured edges (2), ghost state
+    # on boundary edges
     import torch
 
     mesh = box(kind)
     orc, dm = pair(mesh, p, 0)
-    dm.set_surface_mode(dm.SURFACE_EDGEWISE)
+    dm.set_surface_mode(mode)
     C = orc.project(flow) + 0.01 * W.random_state(mesh.n_elem, orc.np, seed=p)
-    case(f"edge-wise dg_rhs + 3 dg_rk_step box={kind} p={p}")
+    case(f"edge-based surface mode {mode}: dg_rhs + 3 dg_rk_step box={kind} p={p}")
     got = dm.unpack(dm.rhs(dm.pack(dev(C)))).cpu().numpy()
     assert rel_l2(got, orc.rhs(C)) <= 1e-11
     dt, _ = orc.max_dt(C, 0.3 / (2 * p + 1))

@@ -27,9 +27,10 @@ def torch_mod():
     return torch
 
 
-ELEMENTWISE, EDGEWISE = 0, 1
+ELEMENTWISE, EDGEWISE, COLOURED = 0, 1, 2
 # surface organisation and work-items per element of the element-wise path
-SURFACE = {"elementwise1": (ELEMENTWISE, 1), "elementwise4": (ELEMENTWISE, 4), "edgewise": (EDGEWISE, 0)}
+SURFACE = {"elementwise1": (ELEMENTWISE, 1), "elementwise4": (ELEMENTWISE, 4), "edgewise": (EDGEWISE, 0),
+           "coloured": (COLOURED, 0)}
 
 
 def gpu_mesh(mesh, p, surface=(ELEMENTWISE, 0)):
@@ -280,12 +281,41 @@ def test_surface_strategies_agree_and_conserve(p):
     a = gpu_rhs(mesh, p, C, SURFACE["elementwise1"])
     b = gpu_rhs(mesh, p, C, SURFACE["edgewise"])
     c = gpu_rhs(mesh, p, C, SURFACE["elementwise4"])
+    d = gpu_rhs(mesh, p, C, SURFACE["coloured"])
     check_close(a, b, 1e-13)
     check_close(c, b, 1e-13)
+    check_close(d, b, 1e-13)
     det = orc.det()
-    for R in (a, b, c):
+    for R in (a, b, c, d):
         terms = det[:, None] * R[:, :, 0]
         assert np.all(np.abs(terms.sum(0)) < 1e-13 * np.abs(terms).sum(0))
+
+
+@pytest.mark.parametrize("p", [1, 3, 5])
+def test_edge_colouring(p):
+    # at most five colours; the coloured edges add into shared accumulators,
+    # so a missed conflict would show as run-to-run differences: two runs
+    # of ten steps agree bit for bit, and with the oracle
+    torch = torch_mod()
+    mesh = W.delaunay_mesh(1500, 50 + p)
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.density_jump)
+    dt, _ = orc.max_dt(C0, 0.3 / (2 * p + 1))
+    dm = gpu_mesh(mesh, p, SURFACE["coloured"])
+    assert 3 <= dm.info.n_colours <= 5
+    case(f"coloured edges x10 twice p={p} colours={dm.info.n_colours}")
+    runs = []
+    for _ in range(2):
+        Cg = dm.pack(to_dev(C0))
+        for _ in range(10):
+            dm.rk_step(Cg, dt)
+        runs.append(Cg)
+    torch.cuda.synchronize()
+    assert torch.equal(runs[0], runs[1])
+    ref = C0
+    for _ in range(10):
+        ref = orc.rk3_step(ref, dt)
+    check_close(dm.unpack(runs[0]).cpu().numpy(), ref)
 
 
 def test_full_size_p3_step_sampled():
