@@ -198,11 +198,15 @@ def run_scale(args):
         dof = dm.n * dm.np * 4
         row = {"p": p, "n_elem": dm.n, "dof": dof}
         finals = {}
-        variants = [("fp64", B.DG_FP64, 0), ("mixed", B.DG_MIXED, 0)]
+        variants = [("fp64", B.DG_FP64, 0, 0), ("mixed", B.DG_MIXED, 0, 0)]
         if not args.no_lane_variants:
-            variants += [("fp64_lanes1", B.DG_FP64, 1), ("fp64_lanes4", B.DG_FP64, 4)]
-        for name, prec, lanes in variants:
+            variants += [("fp64_lanes1", B.DG_FP64, 1, 0), ("fp64_lanes4", B.DG_FP64, 4, 0)]
+        if args.surface_variants:
+            variants += [("fp64_edgewise", B.DG_FP64, 0, dm.SURFACE_EDGEWISE),
+                         ("fp64_coloured", B.DG_FP64, 0, dm.SURFACE_COLOURED)]
+        for name, prec, lanes, surface in variants:
             dm.set_lanes(lanes)
+            dm.set_surface_mode(surface)
             C = C0.clone()
 
             def step(k=1):
@@ -226,6 +230,15 @@ def run_scale(args):
             torch.cuda.synchronize()
             dm.timing(False)
             kt = dm.timing_read()
+            dm.set_surface_mode(dm.SURFACE_ELEMENTWISE)
+            if surface:
+                row[name] = {"value": dof * 3 / (ms * 1e-3), "ms_per_step": ms,
+                             "kernel_ms_per_launch": {k: v[0] / v[1] for k, v in kt.items() if v[1]}}
+                if surface == dm.SURFACE_COLOURED:
+                    row[name]["colours"] = int(dm.info.n_colours)
+                print(f"[scale] p={p} {name}: {row[name]}", file=sys.stderr, flush=True)
+                del C
+                continue
             st_ms = kt["stage"][0] / kt["stage"][1]
             ach = algorithmic_bytes_stage_kernel(dm.n, dm.np, 2.0 / 3.0) / (st_ms * 1e-3) / 1e9
             row[name] = {
@@ -277,6 +290,8 @@ def main():
     ap.add_argument("--orders", default="1,2,3,4,5", help="scale workload orders")
     ap.add_argument("--data", choices=["jump", "smooth"], default="jump", help="scale workload initial data")
     ap.add_argument("--no-lane-variants", action="store_true", help="scale workload: automatic lanes only")
+    ap.add_argument("--surface-variants", action="store_true",
+                    help="scale workload: also time the edge-wise and coloured surface modes (FP64)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(
