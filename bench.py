@@ -115,6 +115,49 @@ def cpu_baseline(mesh, p, seconds: float):
     }
 
 
+def two_stream_edgewise(steps: int):
+    """The paper's suggestion for meshes too small to fill the device: the
+    volume and surface kernels of the edge-wise organisation on two streams.
+    SSP-RK3 steps of the density jump, p = 3, on jittered unit-square meshes
+    of 512 to 32,768 triangles, one stream against two (same results bit for
+    bit), with the fused element-wise step beside them."""
+    import numpy as np
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+    from paper_1601_07944_amd import workloads as W
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    rows = []
+    for n in (16, 32, 64, 128):
+        mesh = W.square_mesh(n, 1.0, 0.2, 7)
+        dm = B.DGMesh.from_mesh(mesh, 3)
+        xy = dm.quad_points().cpu().numpy()
+        C0 = dm.project(torch.from_numpy(np.ascontiguousarray(W.density_jump(xy[..., 0], xy[..., 1]))).cuda())
+        ws = dm.workspace("step")
+        dt_dev, _ = dm.max_dt(C0, 0.3 / 7)
+        row = {"n_elem": dm.n}
+        for name, surface, conc in (("elementwise", dm.SURFACE_ELEMENTWISE, 0), ("edgewise_1stream", dm.SURFACE_EDGEWISE, 0),
+                                    ("edgewise_2streams", dm.SURFACE_EDGEWISE, 1)):
+            dm.set_surface_mode(surface)
+            dm.set_stream_concurrency(conc)
+            C = C0.clone()
+            for _ in range(5):
+                dm.rk_step(C, dt_dev=dt_dev, ws=ws)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                dm.rk_step(C, dt_dev=dt_dev, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            row[name] = e0.elapsed_time(e1) / steps
+        rows.append(row)
+        dm.close()
+    return {"workload": "density jump, p=3, jittered unit square, fixed dt, ms per SSP-RK3 step", "steps": steps,
+            "rows": rows}
+
+
 def limiter_overhead(steps: int):
     """The paper's limiter benchmark (Section "Limiting"): p = 1 steps with
     and without the Barth-Jespersen limiter after every RK stage, here on
@@ -490,6 +533,7 @@ def main():
     dm.set_surface_mode(dm.SURFACE_ELEMENTWISE)
 
     limiter = limiter_overhead(args.steps)
+    streams = two_stream_edgewise(args.steps)
 
     out = {
         "metric": METRIC,
@@ -526,6 +570,7 @@ def main():
         "surface_edgewise": {"ms_per_step": ms_step_edge, "value": dof * 3 / (ms_step_edge * 1e-3)},
         "surface_coloured": {"ms_per_step": ms_step_col, "value": dof * 3 / (ms_step_col * 1e-3),
                              "colours": int(dm.info.n_colours)},
+        "edgewise_two_streams": streams,
         "lanes_per_element": {"headline": 4 if auto4 else 1, "alternative": lanes_alt,
                               "alternative_ms_per_step": ms_step_alt},
         "wall_s_timed_region": wall,

@@ -240,6 +240,21 @@ int dg_quad_weights(dg_mesh m, double* w_dev, void* stream);
 enum { DG_SURFACE_ELEMENTWISE = 0, DG_SURFACE_EDGEWISE = 1, DG_SURFACE_COLOURED = 2 };
 int dg_set_surface_mode(dg_mesh m, int mode);
 
+/* Volume and surface work on two streams in the edge-wise surface mode
+ * (Section "Results" notes that the volume and surface contributions are
+ * independent, so on meshes too small to fill the device the two kernels
+ * can run side by side on separate streams).  With on = 1, every RHS or
+ * RK stage of DG_SURFACE_EDGEWISE runs the volume integral on a library-
+ * owned stream (default priority, created by the first call with on = 1,
+ * destroyed with the mesh) beside the traces and edge fluxes on the
+ * caller's stream; events order it after the work already queued on the
+ * caller's stream, and the element kernel that combines both waits for it,
+ * so the call stays ordered on the caller's stream.  The results equal
+ * those of on = 0 bit for bit.  Other surface modes ignore the setting.
+ * Returns DG_EINVAL for on outside {0, 1}, DG_EHIP if the stream or its
+ * events cannot be created. */
+int dg_set_stream_concurrency(dg_mesh m, int on);
+
 /* Domain boundaries (Section "Surface Integration Kernel": on a boundary
  * edge the right-hand state is a ghost state that depends on the kind of
  * boundary; Section "Mesh Connectivity": boundary sides carry a negative
@@ -330,7 +345,8 @@ enum {
     DG_KERNEL_STAGE = 4,    /* element-wise path: whole RHS (+ RK stage) in one kernel */
     DG_KERNEL_VJP = 5,      /* adjoint of the element-wise RHS (+ RK stage adjoint) */
     DG_KERNEL_LIMIT = 6,    /* slope limiter (p = 1) */
-    DG_KERNEL_KINDS = 7
+    DG_KERNEL_VOLUME = 7,   /* edge-wise path on two streams: volume integral alone */
+    DG_KERNEL_KINDS = 8
 };
 int dg_timing_enable(dg_mesh m, int on);
 int dg_timing_read(dg_mesh m, double* ms, int64_t* count, int n);

@@ -51,6 +51,7 @@ EXPORTS = [
     "dg_quad_weights",
     "dg_set_lanes_per_element",
     "dg_set_surface_mode",
+    "dg_set_stream_concurrency",
     "dg_set_boundary_state",
     "dg_set_integrator",
     "dg_set_limiter",
@@ -119,6 +120,7 @@ def load(path: str = LIB_PATH):
     lib.dg_quad_weights.argtypes = [_vp, _vp, _vp]
     lib.dg_set_lanes_per_element.argtypes = [_vp, i32]
     lib.dg_set_surface_mode.argtypes = [_vp, i32]
+    lib.dg_set_stream_concurrency.argtypes = [_vp, i32]
     lib.dg_set_boundary_state.argtypes = [_vp, _dp]
     lib.dg_set_integrator.argtypes = [_vp, i32]
     lib.dg_set_limiter.argtypes = [_vp, i32]
@@ -290,7 +292,7 @@ class DGMesh:
                                    ctypes.byref(host) if to_host else None, _ptr(ws), _stream(stream)))
         return dt_dev, (host.value if to_host else None)
 
-    KERNELS = ("traces", "edge", "element", "dt", "stage", "vjp", "limit")
+    KERNELS = ("traces", "edge", "element", "dt", "stage", "vjp", "limit", "volume")
     SURFACE_ELEMENTWISE = 0
     SURFACE_EDGEWISE = 1
     SURFACE_COLOURED = 2
@@ -301,6 +303,10 @@ class DGMesh:
 
     def set_surface_mode(self, mode: int):
         _check(self._lib.dg_set_surface_mode(self._h, int(mode)))
+
+    def set_stream_concurrency(self, on: bool):
+        """Edge-wise mode: volume integral on a second stream (bitwise equal)."""
+        _check(self._lib.dg_set_stream_concurrency(self._h, 1 if on else 0))
 
     def set_boundary_state(self, U):
         """Conserved state (rho, rho u, rho v, E) of boundary code DG_BC_STATE."""

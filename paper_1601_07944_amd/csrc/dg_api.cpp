@@ -28,6 +28,12 @@ struct dg_mesh_s {
     int limiter = DG_LIMITER_NONE;
     int integrator = DG_RK_SSP3;
     size_t off_acc = 0;  // RK4 accumulator state in the step workspace
+    size_t off_V = 0;    // volume integral of the two-stream edge-wise path
+    // edge-wise path: volume integral on a second stream beside the traces
+    // and edge fluxes (created by dg_set_stream_concurrency)
+    bool concurrent = false;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool timing = false;
     struct Rec {
         int kind;
@@ -377,18 +383,20 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     const size_t part = align256((size_t)dgk::dt_partials(d) * 8);
     // S: the side slots of the edge-wise mode, or the accumulator state of
     // the coloured mode
+    // V: the volume integral of the two-stream edge-wise path
     const size_t slot = std::max(trace, state);
+    const size_t part4 = align256((size_t)dgk::stage4_partials(d) * 8);
     m->off_T0 = 0;
     m->off_S = trace;
     m->off_part = trace + slot;
-    m->ws_rhs = (int64_t)(trace + slot + part);
-    m->off_T1 = trace + slot + part;
-    m->off_u1 = 2 * trace + slot + part;
-    m->off_u2 = 2 * trace + slot + part + state;
-    m->off_part4 = 2 * trace + slot + part + 2 * state;
-    const size_t part4 = align256((size_t)dgk::stage4_partials(d) * 8);
-    m->off_acc = 2 * trace + slot + part + 2 * state + part4;
-    m->ws_step = (int64_t)(2 * trace + slot + part + 3 * state + part4);
+    m->off_V = trace + slot + part;
+    m->ws_rhs = (int64_t)(m->off_V + state);
+    m->off_T1 = m->off_V + state;
+    m->off_u1 = m->off_T1 + trace;
+    m->off_u2 = m->off_u1 + state;
+    m->off_part4 = m->off_u2 + state;
+    m->off_acc = m->off_part4 + part4;
+    m->ws_step = (int64_t)(m->off_acc + state);
     m->state_bytes = state;
     m->ws_vjp = (int64_t)(4 * state);
     *out = m;
@@ -404,6 +412,12 @@ int dg_mesh_destroy(dg_mesh m)
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : m->pool) (void)hipEventDestroy(e);
+    if (m->side) {
+        (void)hipStreamSynchronize(m->side);
+        (void)hipStreamDestroy(m->side);
+    }
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    if (m->ev_join) (void)hipEventDestroy(m->ev_join);
     for (void* p : m->allocs) (void)hipFree(p);
     delete m;
     return ok();
@@ -456,6 +470,20 @@ void timed(dg_mesh m, int kind, hipStream_t s, F&& launch)
     launch();
     (void)hipEventRecord(r.b, s);
     m->recs.push_back(r);
+}
+
+// Two-stream section of the edge-wise path: fork() makes the side stream
+// wait for the work queued so far on s; join() makes s wait for what was
+// queued on the side stream.
+void fork(dg_mesh m, hipStream_t s)
+{
+    (void)hipEventRecord(m->ev_fork, s);
+    (void)hipStreamWaitEvent(m->side, m->ev_fork, 0);
+}
+void join(dg_mesh m, hipStream_t s)
+{
+    (void)hipEventRecord(m->ev_join, m->side);
+    (void)hipStreamWaitEvent(s, m->ev_join, 0);
 }
 
 }  // namespace
@@ -516,7 +544,18 @@ int dg_rhs(dg_mesh m, const double* C, double* R, dg_precision prec, void* ws, v
         timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s, S); });
         timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_lift(m->dev, T, S, s); });
         timed(m, DG_KERNEL_ELEMENT, s,
-              [&] { dgk::launch_element(m->dev, 0, C, nullptr, R, nullptr, 0.0, nullptr, nullptr, s, S); });
+              [&] { dgk::launch_element(m->dev, 0, C, nullptr, R, nullptr, 0.0, nullptr, nullptr, s, S, 1); });
+        return check_launch("dg_rhs");
+    }
+    if (m->concurrent) {
+        double* V = (double*)(w + m->off_V);
+        fork(m, s);
+        timed(m, DG_KERNEL_VOLUME, m->side, [&] { dgk::launch_volume(m->dev, C, V, m->side); });
+        timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s); });
+        timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(m->dev, T, S, s); });
+        join(m, s);
+        timed(m, DG_KERNEL_ELEMENT, s,
+              [&] { dgk::launch_element(m->dev, 0, C, nullptr, R, S, 0.0, nullptr, nullptr, s, V, 2); });
         return check_launch("dg_rhs");
     }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s); });
@@ -621,11 +660,29 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
     if (m->surface == DG_SURFACE_COLOURED) {
         timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s, S); });
         timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_lift(d, T0, S, s); });
-        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 1, C, nullptr, u1, nullptr, dt, dt_dev, T1, s, S); });
+        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 1, C, nullptr, u1, nullptr, dt, dt_dev, T1, s, S, 1); });
         timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_lift(d, T1, S, s); });
-        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 2, u1, C, u2, nullptr, dt, dt_dev, T0, s, S); });
+        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 2, u1, C, u2, nullptr, dt, dt_dev, T0, s, S, 1); });
         timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_lift(d, T0, S, s); });
-        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 3, u2, C, C, nullptr, dt, dt_dev, nullptr, s, S); });
+        timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 3, u2, C, C, nullptr, dt, dt_dev, nullptr, s, S, 1); });
+        return check_launch("dg_rk_step");
+    }
+    if (m->concurrent) {
+        // per stage: the volume integral of the stage input on the side
+        // stream, beside the traces (stage 1) and edge fluxes on s
+        double* V = (double*)(w + m->off_V);
+        auto stage = [&](int mode, const double* X, const double* U0, double* out, const double* Tin, double* Tn) {
+            fork(m, s);
+            timed(m, DG_KERNEL_VOLUME, m->side, [&] { dgk::launch_volume(d, X, V, m->side); });
+            if (mode == 1) timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, X, T0, s); });
+            timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, Tin, S, s); });
+            join(m, s);
+            timed(m, DG_KERNEL_ELEMENT, s,
+                  [&] { dgk::launch_element(d, mode, X, U0, out, S, dt, dt_dev, Tn, s, V, 2); });
+        };
+        stage(1, C, nullptr, u1, T0, T1);
+        stage(2, u1, C, u2, T1, T0);
+        stage(3, u2, C, C, T0, nullptr);
         return check_launch("dg_rk_step");
     }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s); });
@@ -823,6 +880,20 @@ int dg_set_surface_mode(dg_mesh m, int mode)
     if (mode != DG_SURFACE_ELEMENTWISE && mode != DG_SURFACE_EDGEWISE && mode != DG_SURFACE_COLOURED)
         return fail(DG_EINVAL, "unknown surface mode %d", mode);
     m->surface = mode;
+    return ok();
+}
+
+int dg_set_stream_concurrency(dg_mesh m, int on)
+{
+    if (!m) return fail(DG_EINVAL, "null mesh");
+    if (on != 0 && on != 1) return fail(DG_EINVAL, "stream concurrency is 0 or 1, not %d", on);
+    if (on && !m->side) {
+        hipError_t e = hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "dg_set_stream_concurrency");
+    }
+    m->concurrent = on != 0;
     return ok();
 }
 

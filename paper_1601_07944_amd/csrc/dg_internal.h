@@ -86,11 +86,15 @@ void launch_edge_lift(const MeshDev& m, const double* T, double* R, hipStream_t 
 void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t s);
 // mode 0: R = L(C);   mode 1..3: SSP-RK3 stage (out = stage result);
 // when Tnext != nullptr the traces of `out` are written to it.
-// Racc (optional, coloured edges): take the surface integral from the
-// accumulator instead of lifting the side slots S, and zero it again when
-// Tnext is set (the next stage accumulates into it)
+// src 0: volume integral + side slots S; src 1 (coloured edges): the
+// surface integral from the accumulator Racc + volume integral, Racc zeroed
+// again when Tnext is set (the next stage accumulates into it); src 2: the
+// volume integral from Racc (launch_volume) + side slots S
 void launch_element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
-                    double dt, const double* dt_dev, double* Tnext, hipStream_t s, double* Racc = nullptr);
+                    double dt, const double* dt_dev, double* Tnext, hipStream_t s, double* Racc = nullptr,
+                    int src = 0);
+// the volume integral alone, V = sum over the volume points (before 1/det J)
+void launch_volume(const MeshDev& m, const double* C, double* V, hipStream_t s);
 // fused right-hand side / SSP-RK3 stage (element-wise surface integral);
 // mode as for launch_element, except that mode 3 updates `out` in place
 // (it is the stage-0 state) and U0 must be nullptr

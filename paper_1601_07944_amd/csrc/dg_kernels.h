@@ -314,10 +314,75 @@ __global__ __launch_bounds__(BLOCK) void k_edge_lift(int e0, int e1, int nedge, 
 // ---------------------------------------------------------------- elements
 // The grid covers the padded element count: padding lanes write zeros, so
 // every state this kernel produces has a defined (zero) padding.
-// RACC: the surface integral is already in Racc (coloured edges): start the
-// accumulators from it instead of lifting the side slots S, and zero it
-// again when the next stage's traces are written.
-template <int P, int MODE, bool TRACE, bool RACC>
+// Volume integral eq. (volume) of one element, added to acc:
+// sum_k w_k grad phi_j(r_k) . (adj(J) F(U(r_k))); the point loop stays
+// rolled so only one point's table rows are live.
+template <int P>
+__device__ __forceinline__ void volume_integral(const double (&c)[4][Ord<P>::NP], double a00, double a01, double a10,
+                                                double a11, double gm1, const double* __restrict__ tab,
+                                                double (&acc)[4][Ord<P>::NP])
+{
+    using O = Ord<P>;
+    constexpr int NP = O::NP, NQ = O::NQ;
+#pragma unroll 1
+    for (int k = 0; k < NQ; ++k) {
+        double U[4], Fx[4], Fy[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double u = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) u = fma(tab[O::PHI + k * NP + j], c[m][j], u);
+            U[m] = u;
+        }
+        euler_flux<double>(gm1, U, Fx, Fy);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double gr = a00 * Fx[m] + a01 * Fy[m];
+            const double gs = a10 * Fx[m] + a11 * Fy[m];
+#pragma unroll
+            for (int j = 0; j < NP; ++j)
+                acc[m][j] = fma(tab[O::DRW + k * NP + j], gr, fma(tab[O::DSW + k * NP + j], gs, acc[m][j]));
+        }
+    }
+}
+
+// The volume integral alone, into V (edge-wise path with the volume and
+// surface work on two streams: run beside k_traces / k_edge).
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_volume(int n, const double* __restrict__ C, double* __restrict__ V,
+                                                  const double* __restrict__ geo, const double* __restrict__ tab,
+                                                  double gm1)
+{
+    using O = Ord<P>;
+    constexpr int NP = O::NP;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= n) return;
+    const int so = state_off(e, 4 * NP);
+    const double* g = geo + state_off(e, 6);
+    double c[4][NP], acc[4][NP];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            c[m][j] = C[so + (m * NP + j) * LANES];
+            acc[m][j] = 0.0;
+        }
+    volume_integral<P>(c, g[0], g[LANES], g[2 * LANES], g[3 * LANES], gm1, tab, acc);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) V[so + (m * NP + j) * LANES] = acc[m][j];
+}
+
+// SRC, where the accumulators start and what the kernel adds:
+//   SRC_SLOTS  zero + volume integral + the side slots S (edge-wise);
+//   SRC_RACC   the surface integral in Racc (coloured edges) + volume
+//              integral; Racc is zeroed again when the next stage's traces
+//              are written;
+//   SRC_VOLUME the volume integral in Racc (k_volume on a second stream) +
+//              the side slots S.
+enum { SRC_SLOTS = 0, SRC_RACC = 1, SRC_VOLUME = 2 };
+template <int P, int MODE, bool TRACE, int SRC>
 __global__ __launch_bounds__(BLOCK) void k_element(int n, int npad, const double* __restrict__ C, const double* U0,
                                                    double* out, const double* __restrict__ S,
                                                    const double* __restrict__ geo, const double* __restrict__ tab,
@@ -347,39 +412,18 @@ __global__ __launch_bounds__(BLOCK) void k_element(int n, int npad, const double
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int j = 0; j < NP; ++j) acc[m][j] = RACC ? Racc[so + (m * NP + j) * LANES] : 0.0;
-    if constexpr (RACC && TRACE) {
+        for (int j = 0; j < NP; ++j) acc[m][j] = SRC != SRC_SLOTS ? Racc[so + (m * NP + j) * LANES] : 0.0;
+    if constexpr (SRC == SRC_RACC && TRACE) {
 #pragma unroll
         for (int x = 0; x < 4 * NP; ++x) Racc[so + x * LANES] = 0.0;
     }
 
-    // volume integral: sum_k w_k grad phi_j(r_k) . (adj(J) F(U(r_k)));
-    // the point loop stays rolled so only one point's table rows are live
-#pragma unroll 1
-    for (int k = 0; k < NQ; ++k) {
-        double U[4], Fx[4], Fy[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            double u = 0.0;
-#pragma unroll
-            for (int j = 0; j < NP; ++j) u = fma(tab[O::PHI + k * NP + j], c[m][j], u);
-            U[m] = u;
-        }
-        euler_flux<double>(gm1, U, Fx, Fy);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const double gr = a00 * Fx[m] + a01 * Fy[m];
-            const double gs = a10 * Fx[m] + a11 * Fy[m];
-#pragma unroll
-            for (int j = 0; j < NP; ++j)
-                acc[m][j] = fma(tab[O::DRW + k * NP + j], gr, fma(tab[O::DSW + k * NP + j], gs, acc[m][j]));
-        }
-    }
+    if constexpr (SRC != SRC_VOLUME) volume_integral<P>(c, a00, a01, a10, a11, gm1, tab, acc);
 
     // surface integral: lift the three side slots (already l * omega_k * Fn)
     const int to = state_off(e, 3 * NE * 4);
 #pragma unroll 1
-    for (int qk = 0; qk < (RACC ? 0 : 3 * NE); ++qk) {
+    for (int qk = 0; qk < (SRC == SRC_RACC ? 0 : 3 * NE); ++qk) {
         double sv[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) sv[m] = S[to + (qk * 4 + m) * LANES];
@@ -1610,21 +1654,27 @@ struct Launch {
                                                       m.gamma, m.bc_state);
     }
     static void element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
-                        double dt, const double* dt_dev, double* Tn, hipStream_t s, double* Racc)
+                        double dt, const double* dt_dev, double* Tn, hipStream_t s, double* Racc, int src)
     {
-        if (Racc)
-            element_t<true>(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc);
+        if (src == SRC_RACC)
+            element_t<SRC_RACC>(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc);
+        else if (src == SRC_VOLUME)
+            element_t<SRC_VOLUME>(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc);
         else
-            element_t<false>(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc);
+            element_t<SRC_SLOTS>(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc);
     }
-    template <bool RACC>
+    static void volume(const MeshDev& m, const double* C, double* V, hipStream_t s)
+    {
+        k_volume<P><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, C, V, m.geo, m.tab, m.gamma - 1.0);
+    }
+    template <int SRC>
     static void element_t(const MeshDev& m, int mode, const double* C, const double* U0, double* out,
                           const double* S, double dt, const double* dt_dev, double* Tn, hipStream_t s, double* Racc)
     {
         const double gm1 = m.gamma - 1.0;
         dim3 g = grid_for(m.npad);
 #define DG_ELEM(MODE, TR)                                                                                     \
-    k_element<P, MODE, TR, RACC><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, S, m.geo, m.tab, gm1, dt, dt_dev, \
+    k_element<P, MODE, TR, SRC><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, S, m.geo, m.tab, gm1, dt, dt_dev, \
                                                      Tn, Racc)
         switch (mode) {
         case 0: DG_ELEM(0, false); break;

@@ -66,9 +66,14 @@ void launch_edge_flux(const MeshDev& m, const double* T, double* S, hipStream_t 
 }
 
 void launch_element(const MeshDev& m, int mode, const double* C, const double* U0, double* out, const double* S,
-                    double dt, const double* dt_dev, double* Tn, hipStream_t s, double* Racc)
+                    double dt, const double* dt_dev, double* Tn, hipStream_t s, double* Racc, int src)
 {
-    DG_DISPATCH_P(m.p, element(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc));
+    DG_DISPATCH_P(m.p, element(m, mode, C, U0, out, S, dt, dt_dev, Tn, s, Racc, src));
+}
+
+void launch_volume(const MeshDev& m, const double* C, double* V, hipStream_t s)
+{
+    DG_DISPATCH_P(m.p, volume(m, C, V, s));
 }
 
 void launch_stage(const MeshDev& m, int mode, bool mixed, const double* C, const double* U0, double* out, double dt,

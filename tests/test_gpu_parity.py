@@ -29,8 +29,9 @@ def torch_mod():
 
 ELEMENTWISE, EDGEWISE, COLOURED = 0, 1, 2
 # surface organisation and work-items per element of the element-wise path
+# (third entry: volume integral on a second stream, edge-wise mode)
 SURFACE = {"elementwise1": (ELEMENTWISE, 1), "elementwise4": (ELEMENTWISE, 4), "edgewise": (EDGEWISE, 0),
-           "coloured": (COLOURED, 0)}
+           "edgewise2streams": (EDGEWISE, 0, 1), "coloured": (COLOURED, 0)}
 
 
 def gpu_mesh(mesh, p, surface=(ELEMENTWISE, 0)):
@@ -39,6 +40,8 @@ def gpu_mesh(mesh, p, surface=(ELEMENTWISE, 0)):
     dm = B.DGMesh.from_mesh(mesh, p)
     dm.set_surface_mode(surface[0])
     dm.set_lanes(surface[1])
+    if len(surface) > 2:
+        dm.set_stream_concurrency(surface[2])
     return dm
 
 
@@ -316,6 +319,34 @@ def test_edge_colouring(p):
     for _ in range(10):
         ref = orc.rk3_step(ref, dt)
     check_close(dm.unpack(runs[0]).cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("n,p", [(256, 1), (2000, 3), (16384, 2)])
+def test_two_streams_equal_one_stream(n, p):
+    # the edge-wise path with the volume integral on a second stream gives
+    # the one-stream results bit for bit (right-hand side and ten steps,
+    # twice), and its volume kernel shows up in the per-launch timing
+    torch = torch_mod()
+    mesh = W.delaunay_mesh(n, 60 + p)
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.density_jump)
+    dt, _ = orc.max_dt(C0, 0.3 / (2 * p + 1))
+    one = gpu_mesh(mesh, p, SURFACE["edgewise"])
+    two = gpu_mesh(mesh, p, SURFACE["edgewise2streams"])
+    case(f"edge-wise two streams vs one N={mesh.n_elem} p={p}")
+    Cg = one.pack(to_dev(C0))
+    assert torch.equal(one.rhs(Cg), two.rhs(Cg))
+    two.timing(True)
+    for _ in range(2):
+        A, Bst = Cg.clone(), Cg.clone()
+        for _ in range(10):
+            one.rk_step(A, dt)
+            two.rk_step(Bst, dt)
+        torch.cuda.synchronize()
+        assert torch.equal(A, Bst)
+    kt = two.timing_read()
+    two.timing(False)
+    assert kt["volume"][1] == 60 and kt["element"][1] == 60 and kt["edge"][1] == 60
 
 
 def test_full_size_p3_step_sampled():
