@@ -14,8 +14,12 @@ step / seconds per step, with the state resident in HBM.
 
 Prints ONE JSON line.  Extra objects:
   roofline      the dominant kernel's algorithmic bytes per launch over its
-                average launch time (HIP events around each launch of the
-                timed region), against the 8 TB/s HBM peak;
+                average launch time, against the 8 TB/s HBM peak: the timed
+                region (HIP events on the library's stream around K steps of
+                dg_advance, whose launches are the 3K stage kernels and one
+                step-length reduction) less that reduction's time, over 3K;
+                a second pass with an event pair around every launch gives
+                the per-kernel split (the pairs add ~2 us per launch);
   cpu_baseline  the CPU oracle (serial C, OpenMP element loop) timed on this
                 host on a bounded sample of the same workload;
   rhs_only      dg_rhs alone, DOF-updates/s.
@@ -438,7 +442,9 @@ def main():
     }
     dominant = max(kt, key=lambda k: kt[k][0])
     st_ms, st_n = kt["stage"]
-    ach = algorithmic_bytes_stage_kernel(dm.n, dm.np, 2.0 / 3.0) / (st_ms / st_n * 1e-3) / 1e9
+    assert st_n == 3 * args.steps, kt
+    launch_ms = (ms_step * args.steps - kt["dt"][0]) / (3 * args.steps)
+    ach = algorithmic_bytes_stage_kernel(dm.n, dm.np, 2.0 / 3.0) / (launch_ms * 1e-3) / 1e9
     traffic = load_traffic("stage")
 
     # mixed precision (FP32 contractions/fluxes, FP64 means, update, dt):
@@ -556,7 +562,9 @@ def main():
             "dof": dof,
         },
         "roofline": {
-            "kernel": "k_stage (fused RHS: surface + volume + 1/det J + SSP-RK3 stage)",
+            "kernel": "k_stage4<3, 1..3, double> (fused RHS: surface + volume + 1/det J + SSP-RK3 stage)",
+            "launch_us": launch_ms * 1e3,
+            "launch_us_with_event_pairs": st_ms / st_n * 1e3,
             "bound": "hbm",
             "achieved": ach,
             "peak": HBM_PEAK_GBS,
