@@ -37,6 +37,10 @@ FLAGS = [
     # fma()): the same expression then rounds the same way in every kernel
     # that inlines it, which the bitwise-equality guarantees rely on
     "-ffp-contract=on",
+    # matrix-core instructions keep their operands and results in the
+    # ordinary vector registers (no copies through the accumulation registers)
+    "-mllvm",
+    "-amdgpu-mfma-vgpr-form",
     # packed FP32 instructions stay off: plain scalar/float2 code only
     "-Xclang",
     "-target-feature",

@@ -29,6 +29,12 @@
 
 #include "dg_internal.h"
 
+// 1: the mixed-precision four-lane kernels do their contractions with
+// MFMA; 0: on the vector ALUs like the FP64 kernels
+#ifndef DG_MIXED_MFMA
+#define DG_MIXED_MFMA 1
+#endif
+
 namespace dgk {
 
 template <int P>
@@ -968,6 +974,210 @@ __device__ __forceinline__ void rhs_quad(const Quad4<P, T>& z, const T (&c)[Ord<
     }
 }
 
+// ---------------------------------------------------------------- mixed precision on the matrix cores
+// The FP32 contractions of rhs_quad on v_mfma_f32_4x4x1f32.  That
+// instruction treats every quad of lanes as one 4 x 4 block: register i of
+// lane 4b+j gains A(lane 4b+i) * B(lane 4b+j).  A quad is one element and
+// lane j holds variable j, so with B = a coefficient of the lane's variable
+// and A = a table entry chosen by the lane's position i in the quad, one
+// instruction adds a rank-one term to a 4 x 4 block of every element of the
+// wavefront:
+//   evaluation: A = phi_j(point k0+i), B = c_j: after j = 0..N_p-1, register
+//     i of lane m is variable m at point k0+i (what the scalar path writes
+//     into the exchange slots before its first transpose);
+//   lift: A = w grad phi_{4g+i}(point k) (or the side trace table), B = the
+//     lane's flux component at point k: register i of the accumulator group
+//     g of lane m is mode 4g+i of variable m.
+// The table operands (one value per quad position) come from a copy of the
+// FP32 tables in LDS with the rows padded to multiples of four.
+template <int P>
+struct MTab {
+    using O = Ord<P>;
+    static constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
+    static constexpr int NQ4 = (NQ + 3) / 4 * 4, NE4 = (NE + 3) / 4 * 4, NPP = (NP + 3) / 4 * 4, NG = NPP / 4;
+    // PHI rows k < NQ4 (k >= NQ repeats NQ-1), N_p columns
+    static constexpr int PHI = 0;
+    // w dphi/dr and w dphi/ds rows k < NQ, NPP columns (zero padded)
+    static constexpr int DR = PHI + NQ4 * NP, DS = DR + NQ * NPP;
+    // side traces for evaluation: [q][k < NE4 (k >= NE repeats NE-1)][N_p]
+    static constexpr int PSE = DS + NQ * NPP;
+    // side traces for the lift: [q * NE + k][NPP] (zero padded)
+    static constexpr int PSL = PSE + 3 * NE4 * NP;
+    static constexpr int SIZE = PSL + 3 * NE * NPP;
+};
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// sum_j A_j B_j over a quad block (A = t[j] of the lane's quad position, B =
+// b[j] of the lane's variable) in two independent MFMA chains, even and odd
+// j, added at the end
+template <int NP>
+__device__ __forceinline__ v4f mfma_dot(const float* t, const float (&b)[NP])
+{
+    v4f u0 = {0.f, 0.f, 0.f, 0.f}, u1 = u0;
+#pragma unroll
+    for (int j = 0; j + 1 < NP; j += 2) {
+        u0 = __builtin_amdgcn_mfma_f32_4x4x1f32(t[j], b[j], u0, 0, 0, 0);
+        u1 = __builtin_amdgcn_mfma_f32_4x4x1f32(t[j + 1], b[j + 1], u1, 0, 0, 0);
+    }
+    if constexpr (NP % 2) u0 = __builtin_amdgcn_mfma_f32_4x4x1f32(t[NP - 1], b[NP - 1], u0, 0, 0, 0);
+    return u0 + u1;
+}
+
+template <int P>
+__device__ __forceinline__ void load_mfma_tables(const float* __restrict__ tab, float* t)
+{
+    using O = Ord<P>;
+    using M = MTab<P>;
+    constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE, NPP = M::NPP;
+    for (int x = threadIdx.x; x < M::SIZE; x += BLOCK) {
+        float v;
+        if (x < M::DR) {
+            const int k = x / NP, j = x % NP;
+            v = tab[O::PHI + min(k, NQ - 1) * NP + j];
+        } else if (x < M::PSE) {
+            const int y = x - M::DR, w = y / (NQ * NPP), r = y % (NQ * NPP), k = r / NPP, j = r % NPP;
+            v = j < NP ? tab[(w ? O::DSW : O::DRW) + k * NP + j] : 0.f;
+        } else if (x < M::PSL) {
+            const int y = x - M::PSE, q = y / (M::NE4 * NP), r = y % (M::NE4 * NP), k = r / NP, j = r % NP;
+            v = tab[O::PHS + (q * NE + min(k, NE - 1)) * NP + j];
+        } else {
+            const int y = x - M::PSL, row = y / NPP, j = y % NPP;
+            v = j < NP ? tab[O::PHS + row * NP + j] : 0.f;
+        }
+        t[x] = v;
+    }
+}
+
+// rhs_quad for T = float with the contractions on the matrix cores (same
+// arguments, plus the LDS tables of load_mfma_tables); the fluxes, the
+// exchanges and the FP64 mean mode are those of rhs_quad.
+template <int P, bool BC>
+__device__ __forceinline__ void rhs_quad_mfma(const Quad4<P, float>& z, const float (&c)[Ord<P>::NP],
+                                              const double* Cn, const int* __restrict__ snb,
+                                              const int* __restrict__ sside, const double* __restrict__ sgeo,
+                                              const double* __restrict__ tab64, const float* phs, const float* mt,
+                                              float (&acc)[Ord<P>::NP], double& acc0)
+{
+    using O = Ord<P>;
+    using M = MTab<P>;
+    constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE, NPP = M::NPP, NG = M::NG;
+    constexpr int SS = (NE * NP) | 1;
+    const int e = z.e, m = z.m;
+    Pair<float>* const xr = z.xr;
+    const v4f zero = {0.f, 0.f, 0.f, 0.f};
+    // two accumulator sets (independent MFMA chains): r-derivative and
+    // surface terms in av, s-derivative terms in as
+    v4f av[NG], as[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) av[g] = as[g] = zero;
+    acc0 = 0.0;
+
+    constexpr int PF = 2;
+    const int sides = sside[state_off(e, 1)];
+    const int* const nb = snb + state_off(e, 3);
+    float cn[PF][NP];
+#pragma unroll
+    for (int r = 0; r < PF; ++r) {
+        const int o = state_off(nb[r * LANES], 4 * NP) + m * NP * LANES;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) cn[r][j] = float(Cn[o + j * LANES]);
+    }
+
+    // volume integral, four points at a time (point NQ-1 repeated in the
+    // last group where NQ is not a multiple of 4)
+#pragma unroll 1
+    for (int k0 = 0; k0 < NQ; k0 += 4) {
+        const float* tp = mt + M::PHI + (k0 + m) * NP;  // A: this lane's quad position is its point
+        const v4f u = mfma_dot<NP>(tp, c);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xr[i * XROW + m].a = u[i];
+        wave_sync();
+        float U[4], Fx[4], Fy[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) U[v] = xr[m * XROW + v].a;
+        euler_flux<float>(z.gm1, U, Fx, Fy);
+        wave_sync();
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            xr[m * XROW + v] = Pair<float>{z.a00 * Fx[v] + z.a01 * Fy[v], z.a10 * Fx[v] + z.a11 * Fy[v]};
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = k0 + i;
+            if (k < NQ) {
+                const Pair<float> G = xr[i * XROW + m];
+                const float* tr = mt + M::DR + k * NPP + m;  // A: mode 4g + (quad position)
+                const float* ts = mt + M::DS + k * NPP + m;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    av[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(tr[4 * g], G.a, av[g], 0, 0, 0);
+                    as[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(ts[4 * g], G.b, as[g], 0, 0, 0);
+                }
+            }
+        }
+        wave_sync();
+    }
+
+    // surface integral, per side, its p+1 Gauss points four at a time
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        const int qn = (sides >> (2 * q)) & 3;
+        const int go = state_off(e, 9) + 3 * q * LANES;
+        const float nx = float(sgeo[go]), ny = float(sgeo[go + LANES]);
+        const double hl = sgeo[go + 2 * LANES];
+#pragma unroll 1
+        for (int k0 = 0; k0 < NE; k0 += 4) {
+            // own trace: the side table; neighbour trace: its side's table
+            // with the points reversed (rows past p repeat point p)
+            const float* tl = mt + M::PSE + (q * M::NE4 + k0 + m) * NP;
+            const float* tn = phs + qn * SS + min(k0 + m, NE - 1) * NP;
+            const v4f ul = mfma_dot<NP>(tl, c), ur = mfma_dot<NP>(tn, cn[0]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xr[i * XROW + m] = Pair<float>{ul[i], ur[i]};
+            wave_sync();
+            float UL[4], UR[4], F[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const Pair<float> t = xr[m * XROW + v];
+                UL[v] = t.a;
+                UR[v] = t.b;
+            }
+            if constexpr (BC) ghost_state<float>((z.bcv >> (4 * q)) & 15, UL, nx, ny, z.G, UR);
+            llf<float>(z.gam, z.gm1, UL, UR, nx, ny, F);
+            wave_sync();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xr[m * XROW + v].a = F[v];
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k0 + i;
+                if (k < NE) {
+                    const float Fk = xr[i * XROW + m].a;
+                    const double w = -hl * tab64[O::GW + k];
+                    acc0 = fma(w * tab64[O::PHS + (q * NE + k) * NP], double(Fk), acc0);
+                    const float wf = float(w) * Fk;
+                    const float* ta = mt + M::PSL + (q * NE + k) * NPP + m;
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) av[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(ta[4 * g], wf, av[g], 0, 0, 0);
+                }
+            }
+            wave_sync();
+        }
+#pragma unroll
+        for (int r = 0; r + 1 < PF; ++r)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cn[r][j] = cn[r + 1][j];
+        if (q + PF < 3) {
+            const int nbo = state_off(nb[(q + PF) * LANES], 4 * NP) + m * NP * LANES;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cn[PF - 1][j] = float(Cn[nbo + j * LANES]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) acc[j] = av[j / 4][j % 4] + as[j / 4][j % 4];
+}
+
 // side tables into LDS with the points of each side in reverse order: row k
 // of side q is the trace of mode j at the point that the neighbour across
 // side q sees as its point k (every thread of the block calls it)
@@ -1004,9 +1214,13 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     constexpr int NP = O::NP, NE = O::NE;
     constexpr int SS = (NE * NP) | 1;
     constexpr bool F64 = sizeof(T) == sizeof(double);
+    // the FP32 form runs its contractions on the matrix cores (MFMA)
+    constexpr bool MF = !F64 && DG_MIXED_MFMA;
     __shared__ T phs[3 * SS];
     __shared__ double red[BLOCK / LANES];
     __shared__ Pair<T> xq[(BLOCK / 4) * XQUAD];
+    __shared__ float mt[MF ? MTab<P>::SIZE : 1];
+    if constexpr (MF) load_mfma_tables<P>((const float*)tab, mt);
     load_side_tables<P, T>(tab, phs);
 
     const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -1028,7 +1242,10 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
 #pragma unroll
     for (int j = 0; j < NP; ++j) c[j] = T(C[so + j * LANES]);
     double acc0;
-    rhs_quad<P, T, BC>(z, c, C, snb, sside, sgeo, tab, tab64, phs, acc, acc0);
+    if constexpr (MF)
+        rhs_quad_mfma<P, BC>(z, c, C, snb, sside, sgeo, tab64, phs, mt, acc, acc0);
+    else
+        rhs_quad<P, T, BC>(z, c, C, snb, sside, sgeo, tab, tab64, phs, acc, acc0);
 
     double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
     if constexpr (MODE == 1) {
