@@ -330,6 +330,8 @@ def main():
         help="for rocprofv3 --pmc runs: a few steps of the workload, then a 256 MiB device copy of known size "
         "(the calibration kernel for FETCH_SIZE / WRITE_SIZE); prints nothing else",
     )
+    ap.add_argument("--counter-prec", choices=["fp64", "mixed"], default="fp64",
+                    help="precision of the counter pass's steps")
     ap.add_argument("--workload", choices=["vortex", "scale"], default="vortex",
                     help="vortex: the 32,768-triangle p=3 headline workload (default); scale: per-order sweep at scale")
     ap.add_argument("--mesh", choices=["square", "delaunay"], default="square", help="scale workload mesh")
@@ -343,7 +345,7 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(
             "bench.py measures one GPU: the path runs on a single MI355X; a multi-GPU run "
-            "(element partition + halo exchange) is not part of this build.",
+            "(element partition + halo exchange) is not implemented.",
             file=sys.stderr,
         )
         sys.exit(2)
@@ -388,7 +390,7 @@ def main():
     torch.cuda.synchronize()
     if args.counter_pass:
         for _ in range(args.steps):
-            step()
+            step_prec(C, B.DG_MIXED if args.counter_prec == "mixed" else B.DG_FP64)
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)  # 256 MiB
         b = torch.empty_like(a)
         b.copy_(a)

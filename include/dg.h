@@ -64,7 +64,7 @@ typedef enum {
     DG_EINVAL = -1,        /* null pointer, bad size or bad enum value */
     DG_EMESH = -2,         /* invalid mesh (orientation, connectivity, edges) */
     DG_EORDER = -3,        /* polynomial order outside 1..5 */
-    DG_EUNSUPPORTED = -4,  /* valid input this build does not handle */
+    DG_EUNSUPPORTED = -4,  /* valid input the library does not handle */
     DG_ENOMEM = -5,        /* device allocation failed */
     DG_EHIP = -6,          /* a HIP runtime call or kernel launch failed */
     DG_ENONPHYS = -7       /* non-physical element mean (rho <= 0, p <= 0, NaN) */
