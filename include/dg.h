@@ -266,7 +266,7 @@ int dg_set_stream_concurrency(dg_mesh m, int on);
  *   DG_BC_STATE (-3)    a constant prescribed state (inflow, far field,
  *                       Dirichlet), set with dg_set_boundary_state from the
  *                       host array U[4] = (rho, rho u, rho v, E); until then
- *                       a gas at rest with rho = 1, p = 1 (gamma = 1.4).
+ *                       a gas at rest with rho = 1, p = 1.
  * The local Lax-Friedrichs flux then takes the ghost as its right state.
  * Boundaries are supported by dg_rhs, dg_rk_step and dg_advance in both
  * surface modes and both precisions, and by the limiter (which counts no

@@ -207,9 +207,8 @@ class Oracle:
         self._lib.orc_set_bc_state(self._ctx, _p(U))
 
     def rhs_vjp(self, C, Rbar):
-        """Hand-written adjoint: (dR/dC)^T Rbar (periodic meshes)."""
-        if self.has_boundary:
-            raise NotImplementedError("the oracle's adjoint covers periodic meshes only")
+        """Hand-written adjoint: (dR/dC)^T Rbar (boundary sides through their
+        ghost states)."""
         C = self._state(C)
         Rbar = self._state(Rbar)
         Cb = np.empty_like(C)
@@ -217,9 +216,7 @@ class Oracle:
         return Cb
 
     def rk3_step_vjp(self, C, dt, ubar):
-        """Adjoint of one SSP-RK3 step with fixed dt (periodic meshes)."""
-        if self.has_boundary:
-            raise NotImplementedError("the oracle's adjoint covers periodic meshes only")
+        """Adjoint of one SSP-RK3 step with fixed dt."""
         C = self._state(C)
         ubar = self._state(ubar)
         Cb = np.empty_like(C)

@@ -172,6 +172,10 @@ orc_ctx *orc_create(int p, int64_t n, const double *vxy, const int64_t *nbr, con
     memcpy(c->nbs, nbs, 3 * n);
     for (int64_t x = 0; x < 3 * n; ++x)
         if (nbr[x] < 0) c->has_bc = 1;
+    /* prescribed boundary state until orc_set_bc_state: a gas at rest, rho = 1, p = 1 */
+    c->bc_state[0] = 1.0;
+    c->bc_state[1] = c->bc_state[2] = 0.0;
+    c->bc_state[3] = 1.0 / (gamma - 1.0);
     c->qr = (double *)malloc(sizeof(double) * nq);
     c->qs = (double *)malloc(sizeof(double) * nq);
     c->qw = (double *)malloc(sizeof(double) * nq);
@@ -625,6 +629,25 @@ static void llf_vjp(double gamma, const double UL[M], const double UR[M], double
     }
 }
 
+/* reverse of the ghost state: U_L_bar += (dU_g/dU_L)^T U_g_bar.  The wall's
+ * Jacobian is the reflection diag(1, I - 2 n n^T, 1), its own transpose; the
+ * outflow ghost is the identity; the prescribed state does not depend on U_L.
+ * (At a wall or outflow side the two wave speeds of the flux are the same
+ * function of U_L, so whichever branch of the maximum rounding selects, the
+ * derivative is the same.) */
+static void ghost_vjp(int64_t code, double nx, double ny, const double URb[M], double ULb[M])
+{
+    if (code == -1) {
+        double mnb = URb[1] * nx + URb[2] * ny;
+        ULb[0] += URb[0];
+        ULb[1] += URb[1] - 2.0 * mnb * nx;
+        ULb[2] += URb[2] - 2.0 * mnb * ny;
+        ULb[3] += URb[3];
+    } else if (code == -2) {
+        for (int m = 0; m < M; ++m) ULb[m] += URb[m];
+    }
+}
+
 void orc_rhs_vjp(const orc_ctx *c, const double *C, const double *Rb, double *Cb)
 {
     const int np = c->np, nq = c->nq, ne = c->ne;
@@ -660,12 +683,15 @@ void orc_rhs_vjp(const orc_ctx *c, const double *C, const double *Rb, double *Cb
                 for (int j = 0; j < np; ++j) cbi[m * np + j] += c->phi_v[k * np + j] * Ub[m];
         }
 
-        /* surface: sur[m][j] += l w_k phi_j(r_qk) Fn_m; R has -sur */
+        /* surface: sur[m][j] += l w_k phi_j(r_qk) Fn_m; R has -sur.  On a
+         * domain boundary U_R is the ghost state of U_L, and its cotangent
+         * goes back to U_L through the ghost's Jacobian (ghost_vjp). */
         for (int q = 0; q < 3; ++q) {
             int64_t nb = c->nbr[i * 3 + q];
-            int qn = c->nbs[i * 3 + q];
-            const double *cn = C + nb * M * np;
-            double *cbn = Cb + nb * M * np;
+            const int boundary = nb < 0;
+            int qn = boundary ? 0 : c->nbs[i * 3 + q];
+            const double *cn = C + (boundary ? i : nb) * M * np;
+            double *cbn = Cb + (boundary ? i : nb) * M * np;
             double nx, ny, l;
             side_geometry(c, i, q, &nx, &ny, &l);
             for (int k = 0; k < ne; ++k) {
@@ -681,6 +707,14 @@ void orc_rhs_vjp(const orc_ctx *c, const double *C, const double *Rb, double *Cb
                     }
                     Fb[m] = 0.0;
                     for (int j = 0; j < np; ++j) Fb[m] += -l * c->gw[k] * phiL[j] * Rs[m][j];
+                }
+                if (boundary) {
+                    orc_ghost(c, nb, UL, nx, ny, UR);
+                    llf_vjp(c->gamma, UL, UR, nx, ny, Fb, ULb, URb);
+                    ghost_vjp(nb, nx, ny, URb, ULb);
+                    for (int m = 0; m < M; ++m)
+                        for (int j = 0; j < np; ++j) cbi[m * np + j] += phiL[j] * ULb[m];
+                    continue;
                 }
                 llf_vjp(c->gamma, UL, UR, nx, ny, Fb, ULb, URb);
                 for (int m = 0; m < M; ++m)

@@ -334,7 +334,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     void *d_tab32;
     void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg, *d_snb, *d_sside, *d_sg, *d_sbc, *d_bcs;
     void *d_ecol, *d_egc;
-    const double bc_state0[4] = {1.0, 0.0, 0.0, 2.5};  // until dg_set_boundary_state: gas at rest, p = 1
+    const double bc_state0[4] = {1.0, 0.0, 0.0, 1.0 / (gamma - 1.0)};  // until dg_set_boundary_state: at rest, p = 1
     if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(tab32.data(), tab32.size() * 4, &d_tab32)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
         (rc = upload(vtx.data(), vtx.size() * 8, &d_vtx)) || (rc = upload(perm.data(), perm.size() * 4, &d_perm)) ||
         (rc = upload(el.data(), el.size() * 4, &d_el)) || (rc = upload(er.data(), er.size() * 4, &d_er)) ||

@@ -102,9 +102,45 @@ def test_outflow_free_stream_is_kept():
     assert np.abs(orc.rhs(C)).max() < 1e-12
 
 
-def test_adjoint_refuses_boundaries():
-    box = W.box_mesh(3, 3, 1.0, 1.0, 0.0, 0)
-    orc = O.Oracle(box, 1)
-    C = orc.project(W.free_stream)
-    with pytest.raises(NotImplementedError):
-        orc.rhs_vjp(C, C)
+ADJ_BOXES = {"walls": (W.BC_WALL,) * 4, "outflow": (W.BC_OUTFLOW,) * 4, "state": (W.BC_STATE,) * 4,
+             "channel": (W.BC_STATE, W.BC_OUTFLOW, W.BC_WALL, W.BC_WALL)}
+
+
+def flowing(x, y):
+    # nonzero normal velocity on every side of the unit box
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+    return W.primitive_to_conserved(rho, 0.3 + 0.1 * np.cos(2 * np.pi * y), -0.2 + 0.1 * np.sin(2 * np.pi * x),
+                                    1.0 + 0.1 * np.cos(2 * np.pi * (x + y)))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("kind", sorted(ADJ_BOXES))
+def test_adjoint_through_ghost_states_complex_step(kind, p):
+    # <Rbar, J d> from complex-step derivatives of the forward operator (its
+    # ghost states included) equals <J^T Rbar, d> from the hand-written
+    # adjoint, whose boundary sides go back through the ghost's Jacobian
+    box = W.box_mesh(5, 4, 1.0, 1.0, 0.2, 11, bc=ADJ_BOXES[kind])
+    orc = O.Oracle(box, p)
+    orc.set_bc_state(W.primitive_to_conserved(np.array(1.2), np.array(0.4), np.array(-0.1), np.array(1.1)).reshape(4))
+    C = orc.project(flowing) + 0.01 * W.random_state(box.n_elem, orc.np, seed=p)
+    rng = np.random.default_rng(30 + p)
+    for _ in range(2):
+        d = rng.normal(size=C.shape)
+        Rb = rng.normal(size=C.shape)
+        Jd = orc.rhs_complex(C + 1e-30j * d).imag / 1e-30
+        lhs = np.sum(Rb * Jd)
+        rhs = np.sum(orc.rhs_vjp(C, Rb) * d)
+        assert abs(lhs - rhs) <= 1e-13 * np.abs(Rb * Jd).sum(), (lhs, rhs)
+
+
+def test_adjoint_step_on_a_channel_finite_differences():
+    box = W.box_mesh(6, 5, 1.0, 1.0, 0.2, 12, bc=ADJ_BOXES["channel"])
+    orc = O.Oracle(box, 2)
+    C = orc.project(flowing)
+    dt, _ = orc.max_dt(C, 0.3 / 5)
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=C.shape)
+    ub = rng.normal(size=C.shape)
+    eps = 1e-6
+    fd = (orc.rk3_step(C + eps * d, dt) - orc.rk3_step(C - eps * d, dt)) / (2 * eps)
+    assert abs(np.sum(ub * fd) - np.sum(orc.rk3_step_vjp(C, dt, ub) * d)) <= 1e-8 * np.abs(ub * fd).sum()

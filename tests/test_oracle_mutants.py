@@ -64,6 +64,8 @@ MUTANTS = {
     "wall_half_reflection": ("UR[1] = UL[1] - 2.0 * mn * nx;", "UR[1] = UL[1] - mn * nx;"),
     "outflow_takes_state": ("for (int m = 0; m < M; ++m) UR[m] = UL[m];\n    } else {",
                             "for (int m = 0; m < M; ++m) UR[m] = c->bc_state[m];\n    } else {"),
+    "wall_adjoint_not_mirrored": ("ULb[1] += URb[1] - 2.0 * mnb * nx;", "ULb[1] += URb[1];"),
+    "outflow_adjoint_dropped": ("for (int m = 0; m < M; ++m) ULb[m] += URb[m];", ";"),
     "ghost_from_reversed_point": ("if (boundary) R_NAME(ghost)(c, nb, UL, nx, ny, UR);",
                                   "if (boundary) { R_T Uc[M]; for (int m = 0; m < M; ++m) Uc[m] = UR[m]; "
                                   "R_NAME(ghost)(c, nb, Uc, nx, ny, UR); }"),
@@ -235,7 +237,22 @@ def pin_boundary(lib):
     return bool(ok)
 
 
-PINS = [pin_boundary, pin_rk, pin_limiter, pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
+def pin_boundary_adjoint(lib):
+    # <Rbar, J d> (complex step of the forward, ghosts included) = <J^T Rbar, d>
+    ok = True
+    for bc in ((W.BC_WALL,) * 4, (W.BC_STATE, W.BC_OUTFLOW, W.BC_WALL, W.BC_OUTFLOW)):
+        box = W.box_mesh(4, 3, 1.0, 1.0, 0.2, 21, bc=bc)
+        orc = O.Oracle(box, 1, lib=lib)
+        rng = np.random.default_rng(3)
+        C = W.random_state(box.n_elem, orc.np, seed=6)
+        d = rng.normal(size=C.shape)
+        Rb = rng.normal(size=C.shape)
+        Jd = orc.rhs_complex(C + 1e-30j * d).imag / 1e-30
+        ok &= abs(np.sum(Rb * Jd) - np.sum(orc.rhs_vjp(C, Rb) * d)) <= 1e-13 * np.abs(Rb * Jd).sum()
+    return bool(ok)
+
+
+PINS = [pin_boundary_adjoint, pin_boundary, pin_rk, pin_limiter, pin_adjoint, pin_gram, pin_projection, pin_free_stream, pin_conservation, pin_poly_state, pin_relabel, pin_dt, pin_rk3]
 
 
 def run_pins(lib):
