@@ -272,9 +272,11 @@ int dg_set_stream_concurrency(dg_mesh m, int on);
  * surface modes and both precisions, and by the limiter (which counts no
  * neighbour on a boundary side).  In the edge-wise mode the boundary edges
  * come first in the edge list, grouped by kind, so that whole wavefronts
- * take the same branch.  The adjoint entry points return DG_EUNSUPPORTED on
- * a mesh with boundaries.  dg_set_boundary_state is synchronous and returns
- * DG_EINVAL for a non-physical state. */
+ * take the same branch.  The adjoint entry points (dg_rhs_vjp,
+ * dg_rk_step_vjp) take a boundary side's cotangent back through its ghost
+ * state: the wall's reflection (its own transpose), the outflow's identity;
+ * a prescribed state has none.  dg_set_boundary_state is synchronous and
+ * returns DG_EINVAL for a non-physical state. */
 enum { DG_BC_WALL = -1, DG_BC_OUTFLOW = -2, DG_BC_STATE = -3 };
 int dg_set_boundary_state(dg_mesh m, const double* U);
 

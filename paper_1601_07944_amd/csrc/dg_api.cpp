@@ -698,7 +698,6 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
 int dg_rhs_vjp(dg_mesh m, const double* C, const double* Rb, double* Cb, void* ws, void* stream)
 {
     if (!m || !C || !Rb || !Cb) return fail(DG_EINVAL, "null argument");
-    if (m->dev.has_bc) return fail(DG_EUNSUPPORTED, "the adjoint covers periodic meshes only");
     (void)ws;
     hipStream_t s = (hipStream_t)stream;
     timed(m, DG_KERNEL_VJP, s,
@@ -792,7 +791,6 @@ int dg_rk_step_vjp(dg_mesh m, const double* C, double dt, const double* dt_dev, 
     if (m->limiter != DG_LIMITER_NONE)
         return fail(DG_EUNSUPPORTED, "the limited step is not differentiable; switch the limiter off");
     if (m->integrator != DG_RK_SSP3) return fail(DG_EUNSUPPORTED, "the step adjoint is that of SSP-RK3");
-    if (m->dev.has_bc) return fail(DG_EUNSUPPORTED, "the adjoint covers periodic meshes only");
     hipStream_t s = (hipStream_t)stream;
     const dgk::MeshDev& d = m->dev;
     char* w = (char*)ws;

@@ -1412,24 +1412,79 @@ __device__ __forceinline__ void llf_vjp_left(double gamma, double gm1, const dou
     }
 }
 
+// Cotangent of the local Lax-Friedrichs flux with respect to its right
+// state: 1/2 A_n(UR)^T Fb - lambda/2 Fb - (sum_m Fb_m (UR_m - UL_m))/2
+// d lambda_R/d UR, the last term only when lambda_R > lambda_L (ties take
+// the left branch, as in llf_vjp_left).
+__device__ __forceinline__ void llf_vjp_right(double gamma, double gm1, const double UL[4], const double UR[4],
+                                              double nx, double ny, const double Fb[4], double Ub[4])
+{
+    const double riL = recip(UL[0]), riR = recip(UR[0]);
+    const double uL = UL[1] * riL, vL = UL[2] * riL, uR = UR[1] * riR, vR = UR[2] * riR;
+    const double pL = gm1 * (UL[3] - 0.5 * (UL[1] * uL + UL[2] * vL));
+    const double pR = gm1 * (UR[3] - 0.5 * (UR[1] * uR + UR[2] * vR));
+    const double vnL = uL * nx + vL * ny, vnR = uR * nx + vR * ny;
+    const double cL = root(gamma * pL * riL), cR = root(gamma * pR * riR);
+    const double lamL = fabs(vnL) + cL, lamR = fabs(vnR) + cR;
+    const double lam = fmax(lamL, lamR);
+    double X[4], Y[4], jump = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        X[m] = 0.5 * nx * Fb[m];
+        Y[m] = 0.5 * ny * Fb[m];
+        Ub[m] += -0.5 * lam * Fb[m];
+        jump += Fb[m] * (UR[m] - UL[m]);
+    }
+    flux_vjp(gm1, UR, X, Y, Ub);
+    const double lb = lamL >= lamR ? 0.0 : -0.5 * jump;  // cotangent of lambda_R
+    const double sv = vnR >= 0.0 ? lb : -lb;
+    const double pb = lb * cR / (2.0 * pR);
+    Ub[0] += -sv * vnR * riR - lb * cR * riR * 0.5 + pb * gm1 * 0.5 * (uR * uR + vR * vR);
+    Ub[1] += sv * nx * riR - pb * gm1 * uR;
+    Ub[2] += sv * ny * riR - pb * gm1 * vR;
+    Ub[3] += pb * gm1;
+}
+
+// Cotangent of the flux on a side of kind bc (0 interior: llf_vjp_left
+// alone; the neighbour adds its own part in gather form) with U_R the ghost
+// state of U_L: the left cotangent plus the right one taken back through the
+// ghost's Jacobian, the wall's reflection (its own transpose), the outflow's
+// identity, or nothing for a prescribed state.  Selects, not branches.
+__device__ __forceinline__ void llf_vjp_side(int bc, double gamma, double gm1, const double UL[4], const double UR[4],
+                                             double nx, double ny, const double Fb[4], double Ub[4])
+{
+    llf_vjp_left(gamma, gm1, UL, UR, nx, ny, Fb, Ub);
+    double Vb[4] = {0.0, 0.0, 0.0, 0.0};
+    llf_vjp_right(gamma, gm1, UL, UR, nx, ny, Fb, Vb);
+    const double s = bc == 1 ? 2.0 * (Vb[1] * nx + Vb[2] * ny) : 0.0;
+    const bool back = bc == 1 || bc == 2;
+    Ub[0] += back ? Vb[0] : 0.0;
+    Ub[1] += back ? Vb[1] - s * nx : 0.0;
+    Ub[2] += back ? Vb[2] - s * ny : 0.0;
+    Ub[3] += back ? Vb[3] : 0.0;
+}
+
 // Vector-Jacobian product of the fused right-hand side, element-wise in
 // gather form.  For element i the cotangent of its side trace at point k is
 //   J_L(U_i, U_nb, n_i)^T (Fb_i(q, k) - Fb_nb(qn, p-k)),
 // because the neighbour's flux on the shared edge is F(U_nb, U_i, -n_i) =
 // -F(U_i, U_nb, n_i); Fb = -l omega_k (trace of Rbar/det J) on each side.
-// So no cotangent is scattered into another element.
+// So no cotangent is scattered into another element.  A domain-boundary
+// side (BC variant) has no neighbour flux: Fb is the element's own, U_R is
+// the ghost of U_L, and the ghost's cotangent returns to U_L (llf_vjp_side).
 //   MODE 0: out = J(C)^T Rb
 //   MODE 1: out = 2/3 Rb + 2/3 dt J(C)^T Rb          (adjoint of RK stage 3)
 //   MODE 2: out = 1/4 Rb + 1/4 dt J(C)^T Rb          (adjoint of RK stage 2)
 //   MODE 3: out = 1/3 X + 3/4 Y + Rb + dt J(C)^T Rb  (adjoint of RK stage 1)
-template <int P, int MODE>
+template <int P, int MODE, bool BC>
 __global__ __launch_bounds__(BLOCK) void k_stage_vjp(int n, int npad, const double* __restrict__ C,
                                                      const double* __restrict__ Rb, const double* __restrict__ X,
                                                      const double* __restrict__ Y, double* __restrict__ out,
                                                      const double* __restrict__ geo, const int* __restrict__ snb,
                                                      const int* __restrict__ sside, const double* __restrict__ sgeo,
                                                      const double* __restrict__ tab, double gamma, double dt,
-                                                     const double* __restrict__ dt_dev)
+                                                     const double* __restrict__ dt_dev, const int* __restrict__ sbc,
+                                                     const double* __restrict__ bcs)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
@@ -1486,10 +1541,15 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp(int n, int npad, const doub
 
     // surface
     const int sides = sside[state_off(e, 1)];
+    const int bcv = BC ? sbc[state_off(e, 1)] : 0;
+    double G[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) G[m] = BC ? bcs[m] : 0.0;
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
         const int nb = snb[state_off(e, 3) + q * LANES];
         const int qn = (sides >> (2 * q)) & 3;
+        const int bc = (bcv >> (4 * q)) & 15;
         const int go = state_off(e, 9) + 3 * q * LANES;
         const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
         const double idn = geo[state_off(nb, 6) + 4 * LANES];
@@ -1532,9 +1592,14 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp(int n, int npad, const doub
                     r = fma(tl[j], rs[m][j], r);
                 }
                 UL[m] = u;
-                Fb[m] = w * (r - RR[k][m]);
+                Fb[m] = w * (r - (bc ? 0.0 : RR[k][m]));
             }
-            llf_vjp_left(gamma, gm1, UL, UR[k], nx, ny, Fb, Ub);
+            if constexpr (BC) {
+                ghost_state<double>(bc, UL, nx, ny, G, UR[k]);
+                llf_vjp_side(bc, gamma, gm1, UL, UR[k], nx, ny, Fb, Ub);
+            } else {
+                llf_vjp_left(gamma, gm1, UL, UR[k], nx, ny, Fb, Ub);
+            }
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -1566,14 +1631,15 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp(int n, int npad, const doub
 // through LDS let lane i evaluate the full closed-form cotangent (flux_vjp,
 // llf_vjp_left) at point i once and hand component m back to lane m.
 // Modes as k_stage_vjp.
-template <int P, int MODE>
+template <int P, int MODE, bool BC>
 __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const double* __restrict__ C,
                                                       const double* __restrict__ Rb, const double* __restrict__ X,
                                                       const double* __restrict__ Y, double* __restrict__ out,
                                                       const double* __restrict__ geo, const int* __restrict__ snb,
                                                       const int* __restrict__ sside, const double* __restrict__ sgeo,
                                                       const double* __restrict__ tab, double gamma, double dt,
-                                                      const double* __restrict__ dt_dev)
+                                                      const double* __restrict__ dt_dev, const int* __restrict__ sbc,
+                                                      const double* __restrict__ bcs)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
@@ -1661,9 +1727,14 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const dou
     }
 
     // surface: traces of both sides and the flux cotangent Fb at four points
+    const int bcv = BC ? sbc[state_off(e, 1)] : 0;
+    double G[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) G[v] = BC ? bcs[v] : 0.0;
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
         const int qn = (sides >> (2 * q)) & 3;
+        const int bc = (bcv >> (4 * q)) & 15;
         const int go = state_off(e, 9) + 3 * q * LANES;
         const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
         const lds_ptr<double> tq = lds_row(phs, qn * SS);
@@ -1678,7 +1749,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const dou
                 const double ul = dot2<NP>(tl, c), rl = dot2<NP>(tl, rs);
                 const double ur = dot2<NP>(tq + k * NP, cn[0]), rr = dot2<NP>(tq + k * NP, rn[0]);
                 ra[i * XROW + m] = Pair<double>{ul, ur};
-                rb[i * XROW + m].a = -hl * tab[O::GW + k] * (rl - rr);
+                rb[i * XROW + m].a = -hl * tab[O::GW + k] * (rl - (bc ? 0.0 : rr));
             }
             wave_sync();
             double UL[4], UR[4], Fb[4], Ub[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1689,7 +1760,12 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const dou
                 UR[v] = t.b;
                 Fb[v] = rb[m * XROW + v].a;
             }
-            llf_vjp_left(gamma, gm1, UL, UR, nx, ny, Fb, Ub);
+            if constexpr (BC) {
+                ghost_state<double>(bc, UL, nx, ny, G, UR);
+                llf_vjp_side(bc, gamma, gm1, UL, UR, nx, ny, Fb, Ub);
+            } else {
+                llf_vjp_left(gamma, gm1, UL, UR, nx, ny, Fb, Ub);
+            }
             wave_sync();
 #pragma unroll
             for (int v = 0; v < 4; ++v) ra[m * XROW + v].a = Ub[v];
@@ -1945,11 +2021,20 @@ struct Launch {
     static void stage_vjp(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X,
                           const double* Y, double* out, double dt, const double* dt_dev, hipStream_t s)
     {
+        if (m.has_bc)
+            stage_vjp_t<true>(m, mode, C, Rb, X, Y, out, dt, dt_dev, s);
+        else
+            stage_vjp_t<false>(m, mode, C, Rb, X, Y, out, dt, dt_dev, s);
+    }
+    template <bool BC>
+    static void stage_vjp_t(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X,
+                            const double* Y, double* out, double dt, const double* dt_dev, hipStream_t s)
+    {
         if (m.lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
-#define DG_VJP4(MODE)                                                                                              \
-    k_stage_vjp4<P, MODE><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, Rb, X, Y, out, m.geo, m.side_nb, m.side_q, m.side_g, \
-                                               m.tab, m.gamma, dt, dt_dev)
+#define DG_VJP4(MODE)                                                                                                  \
+    k_stage_vjp4<P, MODE, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, Rb, X, Y, out, m.geo, m.side_nb, m.side_q, m.side_g, \
+                                                   m.tab, m.gamma, dt, dt_dev, m.side_bc, m.bc_state)
             switch (mode) {
             case 0: DG_VJP4(0); break;
             case 1: DG_VJP4(1); break;
@@ -1961,9 +2046,9 @@ struct Launch {
         }
         const int nb = (m.npad + BLOCK - 1) / BLOCK;
         dim3 g((nb + 7) / 8 * 8);
-#define DG_VJP(MODE)                                                                                             \
-    k_stage_vjp<P, MODE><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, Rb, X, Y, out, m.geo, m.side_nb, m.side_q, m.side_g, \
-                                             m.tab, m.gamma, dt, dt_dev)
+#define DG_VJP(MODE)                                                                                                 \
+    k_stage_vjp<P, MODE, BC><<<g, BLOCK, 0, s>>>(m.n, m.npad, C, Rb, X, Y, out, m.geo, m.side_nb, m.side_q, m.side_g, \
+                                                 m.tab, m.gamma, dt, dt_dev, m.side_bc, m.bc_state)
         switch (mode) {
         case 0: DG_VJP(0); break;
         case 1: DG_VJP(1); break;
