@@ -350,6 +350,9 @@ def main():
         )
         sys.exit(2)
 
+    from paper_1601_07944_amd import build as Bd
+
+    Bd.ensure_built()
     if args.workload == "scale":
         run_scale(args)
         return

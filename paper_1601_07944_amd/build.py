@@ -81,3 +81,9 @@ def build(verbose: bool = False, extra=(), jobs: int | None = None) -> str:
 
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv, extra=[a for a in sys.argv[1:] if a != "-v"]))
+
+
+def ensure_built() -> str:
+    """Build libdgmi.so only if there is none (tests, smoke and the benchmark
+    use whatever is built; build() always compiles)."""
+    return LIB if os.path.exists(LIB) else build()

@@ -10,6 +10,9 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
+    from paper_1601_07944_amd import build
+
+    build.ensure_built()
 
 
 def _has_gpu():
