@@ -275,8 +275,9 @@ int dg_set_stream_concurrency(dg_mesh m, int on);
  * take the same branch.  The adjoint entry points (dg_rhs_vjp,
  * dg_rk_step_vjp) take a boundary side's cotangent back through its ghost
  * state: the wall's reflection (its own transpose), the outflow's identity;
- * a prescribed state has none.  dg_set_boundary_state is synchronous and
- * returns DG_EINVAL for a non-physical state. */
+ * a prescribed state has none.  dg_set_boundary_state waits for all work
+ * on the device, then copies the state (the next calls on any stream see
+ * it); it returns DG_EINVAL for a non-physical state. */
 enum { DG_BC_WALL = -1, DG_BC_OUTFLOW = -2, DG_BC_STATE = -3 };
 int dg_set_boundary_state(dg_mesh m, const double* U);
 

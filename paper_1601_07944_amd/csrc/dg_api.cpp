@@ -475,15 +475,15 @@ void timed(dg_mesh m, int kind, hipStream_t s, F&& launch)
 // Two-stream section of the edge-wise path: fork() makes the side stream
 // wait for the work queued so far on s; join() makes s wait for what was
 // queued on the side stream.
-void fork(dg_mesh m, hipStream_t s)
+hipError_t fork(dg_mesh m, hipStream_t s)
 {
-    (void)hipEventRecord(m->ev_fork, s);
-    (void)hipStreamWaitEvent(m->side, m->ev_fork, 0);
+    hipError_t e = hipEventRecord(m->ev_fork, s);
+    return e == hipSuccess ? hipStreamWaitEvent(m->side, m->ev_fork, 0) : e;
 }
-void join(dg_mesh m, hipStream_t s)
+hipError_t join(dg_mesh m, hipStream_t s)
 {
-    (void)hipEventRecord(m->ev_join, m->side);
-    (void)hipStreamWaitEvent(s, m->ev_join, 0);
+    hipError_t e = hipEventRecord(m->ev_join, m->side);
+    return e == hipSuccess ? hipStreamWaitEvent(s, m->ev_join, 0) : e;
 }
 
 }  // namespace
@@ -549,11 +549,12 @@ int dg_rhs(dg_mesh m, const double* C, double* R, dg_precision prec, void* ws, v
     }
     if (m->concurrent) {
         double* V = (double*)(w + m->off_V);
-        fork(m, s);
+        hipError_t e = fork(m, s);
+        if (e != hipSuccess) return hip_fail(e, "dg_rhs (stream fork)");
         timed(m, DG_KERNEL_VOLUME, m->side, [&] { dgk::launch_volume(m->dev, C, V, m->side); });
         timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(m->dev, C, T, s); });
         timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(m->dev, T, S, s); });
-        join(m, s);
+        if ((e = join(m, s)) != hipSuccess) return hip_fail(e, "dg_rhs (stream join)");
         timed(m, DG_KERNEL_ELEMENT, s,
               [&] { dgk::launch_element(m->dev, 0, C, nullptr, R, S, 0.0, nullptr, nullptr, s, V, 2); });
         return check_launch("dg_rhs");
@@ -671,18 +672,22 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
         // per stage: the volume integral of the stage input on the side
         // stream, beside the traces (stage 1) and edge fluxes on s
         double* V = (double*)(w + m->off_V);
-        auto stage = [&](int mode, const double* X, const double* U0, double* out, const double* Tin, double* Tn) {
-            fork(m, s);
+        auto stage = [&](int mode, const double* X, const double* U0, double* out, const double* Tin,
+                         double* Tn) -> hipError_t {
+            hipError_t e = fork(m, s);
+            if (e != hipSuccess) return e;
             timed(m, DG_KERNEL_VOLUME, m->side, [&] { dgk::launch_volume(d, X, V, m->side); });
             if (mode == 1) timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, X, T0, s); });
             timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, Tin, S, s); });
-            join(m, s);
+            if ((e = join(m, s)) != hipSuccess) return e;
             timed(m, DG_KERNEL_ELEMENT, s,
                   [&] { dgk::launch_element(d, mode, X, U0, out, S, dt, dt_dev, Tn, s, V, 2); });
+            return hipSuccess;
         };
-        stage(1, C, nullptr, u1, T0, T1);
-        stage(2, u1, C, u2, T1, T0);
-        stage(3, u2, C, C, T0, nullptr);
+        hipError_t e = stage(1, C, nullptr, u1, T0, T1);
+        if (e == hipSuccess) e = stage(2, u1, C, u2, T1, T0);
+        if (e == hipSuccess) e = stage(3, u2, C, C, T0, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "dg_rk_step (stream fork / join)");
         return check_launch("dg_rk_step");
     }
     timed(m, DG_KERNEL_TRACES, s, [&] { dgk::launch_traces(d, C, T0, s); });
@@ -838,7 +843,10 @@ int dg_set_boundary_state(dg_mesh m, const double* U)
     if (!m || !U) return fail(DG_EINVAL, "null argument");
     const double rho = U[0], p = (m->dev.gamma - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / rho);
     if (!(rho > 0.0) || !(p > 0.0)) return fail(DG_EINVAL, "boundary state is not physical (rho = %g, p = %g)", rho, p);
-    hipError_t e = hipMemcpy(m->dev.bc_state, U, 4 * sizeof(double), hipMemcpyHostToDevice);
+    // the state is read by kernels that may still be running on any stream:
+    // let them finish before it changes
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(m->dev.bc_state, U, 4 * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "dg_set_boundary_state");
     return ok();
 }
