@@ -78,11 +78,16 @@ def test_limited_steps_match_oracle(lanes):
     case(f"limited dg_rk_step x20 lanes={lanes}")
     Cg = dm.pack(dev(C0))
     ref = C0
+    dm.timing(True)
     for _ in range(20):
         dm.rk_step(Cg, dt)
         ref = orc.rk3_step(ref, dt, limit=True)
     torch.cuda.synchronize()
+    dm.timing(False)
+    kt = dm.timing_read()
     assert rel_l2(dm.unpack(Cg).cpu().numpy(), ref) <= 1e-11
+    # a limiter pass after every stage
+    assert kt["limit"][1] == 60, kt
     # and it is not the unlimited step
     un = C0
     for _ in range(20):
