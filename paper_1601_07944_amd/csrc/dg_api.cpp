@@ -77,16 +77,28 @@ int n_vol_points(int p)
     return nq[p];
 }
 
-// 21-bit interleave for a 42-bit Morton key
-uint64_t spread(uint64_t v)
+// Position of grid cell (x, y), 0 <= x, y < 2^21, along the Hilbert curve
+// that fills the 2^21 x 2^21 grid: quadrant by quadrant from the coarsest
+// level, each quadrant's frame rotated / reflected so that consecutive cells
+// are always edge neighbours (unlike a Morton curve, which jumps).
+uint64_t hilbert_key(uint64_t x, uint64_t y)
 {
-    v &= 0x1fffff;
-    v = (v | v << 32) & 0x1f00000000ffffULL;
-    v = (v | v << 16) & 0x1f0000ff0000ffULL;
-    v = (v | v << 8) & 0x100f00f00f00f00fULL;
-    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
-    v = (v | v << 2) & 0x1249249249249249ULL;
-    return v;
+    const uint64_t n = 1ULL << 21;
+    uint64_t d = 0;
+    for (uint64_t s = n >> 1; s > 0; s >>= 1) {
+        const uint64_t rx = (x & s) ? 1 : 0, ry = (y & s) ? 1 : 0;
+        d += s * s * ((3 * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = (n - 1) - x;
+                y = (n - 1) - y;
+            }
+            const uint64_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
 }
 
 }  // namespace
@@ -160,7 +172,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     const int np = dgh::n_modes(p), ne = p + 1, nq = n_vol_points(p);
     const int N = (int)n, npad = (N + 63) / 64 * 64;
 
-    // element order along a Morton curve of the centroids
+    // element order along a Hilbert curve of the centroids
     std::vector<double> cx(N), cy(N);
     double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
     for (int i = 0; i < N; ++i) {
@@ -177,7 +189,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     for (int i = 0; i < N; ++i) {
         uint64_t qx = (uint64_t)std::min(2097151.0, std::floor((cx[i] - xmin) / span * 2097151.0));
         uint64_t qy = (uint64_t)std::min(2097151.0, std::floor((cy[i] - ymin) / span * 2097151.0));
-        key[i] = spread(qx) | (spread(qy) << 1);
+        key[i] = hilbert_key(qx, qy);
     }
     std::vector<int> perm(N), inv(N);
     std::iota(perm.begin(), perm.end(), 0);
