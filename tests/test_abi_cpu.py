@@ -111,3 +111,50 @@ def test_library_tables_match_oracle(p):
         x = t["gx"]
         rr, ss = {0: ((1 + x) / 2, 0 * x), 1: ((1 - x) / 2, (1 + x) / 2), 2: (0 * x, (1 - x) / 2)}[q]
         assert np.abs(t["phi_side"][q] - O.basis(p, rr, ss)[0]).max() < 1e-13
+
+
+def test_validate_rejects_empty_mesh():
+    # zero elements: an error, not an empty operator
+    empty = np.zeros((0, 3, 2))
+    assert B.validate(1, empty, np.zeros((0, 3), dtype=np.int64), np.zeros((0, 3), dtype=np.int8)) == -1
+
+
+def test_validate_rejects_degenerate_element():
+    # a triangle of zero area (collinear vertices) is rejected like an
+    # inverted one
+    m = good_mesh()
+    v = m.vxy.copy()
+    v[0, 2] = 0.5 * (v[0, 0] + v[0, 1])
+    assert B.validate(1, v, m.nbr_elem, m.nbr_side) == -2
+
+
+def test_null_and_bad_arguments_are_errors_not_crashes():
+    lib = B.load()
+    import ctypes
+
+    out = ctypes.c_void_p()
+    m = good_mesh()
+    vxy = np.ascontiguousarray(m.vxy)
+    # null arrays
+    assert lib.dg_mesh_create(1, m.n_elem, None, None, None, 1.4, ctypes.byref(out)) == -1
+    # order outside 1..5 is rejected before any device call
+    nb = np.ascontiguousarray(m.nbr_elem, dtype=np.int64)
+    ns = np.ascontiguousarray(m.nbr_side, dtype=np.int8)
+    assert lib.dg_mesh_create(6, m.n_elem, vxy.ctypes.data, nb.ctypes.data, ns.ctypes.data, 1.4, ctypes.byref(out)) == -3
+    # the entry points refuse a null mesh
+    assert lib.dg_rhs(None, None, None, 0, None, None) == -1
+    assert lib.dg_set_surface_mode(None, 0) == -1
+    assert lib.dg_set_stream_concurrency(None, 1) == -1
+    assert lib.dg_set_boundary_state(None, None) == -1
+    assert b"null" in lib.dg_last_error()
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # no CPU fallback: a missing library is an error
+    saved = B._lib
+    B._lib = None
+    try:
+        with pytest.raises(RuntimeError):
+            B.load(str(tmp_path / "libdgmi.so"))
+    finally:
+        B._lib = saved
