@@ -196,7 +196,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
     for (int i = 0; i < N; ++i) inv[perm[i]] = i;
 
-    // geometry [blk][6][64] and vertices (internal order)
+    // geometry [blk][6][LANES] and vertices (internal order)
     std::vector<double> geo((size_t)npad * 6, 0.0), vtx((size_t)npad * 6, 0.0);
     for (int i = 0; i < N; ++i) {
         const double* v = vxy + 6 * perm[i];
@@ -207,13 +207,13 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
             double dx = v[2 * ((q + 1) % 3)] - v[2 * q], dy = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
             per += std::sqrt(dx * dx + dy * dy);
         }
-        const size_t b = (size_t)(i / 64) * 6 * 64 + (i % 64);
-        geo[b + 0 * 64] = y3 - y1;     // adj(J) = det J * J^{-1}
-        geo[b + 1 * 64] = -(x3 - x1);
-        geo[b + 2 * 64] = -(y2 - y1);
-        geo[b + 3 * 64] = x2 - x1;
-        geo[b + 4 * 64] = 1.0 / det;
-        geo[b + 5 * 64] = det / per;   // inscribed radius
+        const size_t b = (size_t)(i / dgk::LANES) * 6 * dgk::LANES + (i % dgk::LANES);
+        geo[b + 0 * dgk::LANES] = y3 - y1;     // adj(J) = det J * J^{-1}
+        geo[b + 1 * dgk::LANES] = -(x3 - x1);
+        geo[b + 2 * dgk::LANES] = -(y2 - y1);
+        geo[b + 3 * dgk::LANES] = x2 - x1;
+        geo[b + 4 * dgk::LANES] = 1.0 / det;
+        geo[b + 5 * dgk::LANES] = det / per;   // inscribed radius
         std::memcpy(&vtx[(size_t)i * 6], v, 6 * sizeof(double));
     }
 
@@ -301,7 +301,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     for (int i = 0; i < N; ++i) {
         const int u = perm[i];
         const double* v = vxy + 6 * u;
-        const size_t b = (size_t)(i / 64) * 64;
+        const size_t b = (size_t)(i / dgk::LANES) * dgk::LANES;
         int packed = 0, bcs = 0;
         for (int q = 0; q < 3; ++q) {
             double dx = v[2 * ((q + 1) % 3)] - v[2 * q], dy = v[2 * ((q + 1) % 3) + 1] - v[2 * q + 1];
@@ -310,17 +310,17 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
             if (nq < 0) {
                 has_bc = true;
                 bcs |= (int)(-nq) << (4 * q);
-                snb[b * 3 + q * 64 + i % 64] = i;
+                snb[b * 3 + q * dgk::LANES + i % dgk::LANES] = i;
             } else {
-                snb[b * 3 + q * 64 + i % 64] = inv[nq];
+                snb[b * 3 + q * dgk::LANES + i % dgk::LANES] = inv[nq];
                 packed |= nbs[3 * u + q] << (2 * q);
             }
-            sg[b * 9 + (3 * q + 0) * 64 + i % 64] = dy / len;
-            sg[b * 9 + (3 * q + 1) * 64 + i % 64] = -dx / len;
-            sg[b * 9 + (3 * q + 2) * 64 + i % 64] = 0.5 * len;
+            sg[b * 9 + (3 * q + 0) * dgk::LANES + i % dgk::LANES] = dy / len;
+            sg[b * 9 + (3 * q + 1) * dgk::LANES + i % dgk::LANES] = -dx / len;
+            sg[b * 9 + (3 * q + 2) * dgk::LANES + i % dgk::LANES] = 0.5 * len;
         }
-        sside[b + i % 64] = packed;
-        sbc[b + i % 64] = bcs;
+        sside[b + i % dgk::LANES] = packed;
+        sbc[b + i % dgk::LANES] = bcs;
     }
 
     dgh::TableLayout lay;

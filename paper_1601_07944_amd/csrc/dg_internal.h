@@ -25,15 +25,19 @@ std::vector<double> build_tables(int p, TableLayout* lay);
 
 namespace dgk {
 
-// Elements are processed in blocks of 64 (one wavefront); every per-element
-// array is stored block-major: [block][field][lane], lane = element % 64.
-constexpr int LANES = 64;
+// Every per-element array is stored block-major in blocks of LANES = 16
+// elements: [block][field][lane], lane = element % 16, so one field of a
+// block is a 128-byte row of doubles.  (A neighbour gather touches one row
+// per field; 16-element rows keep that footprint small while a wavefront of
+// one-lane kernels still reads whole rows.)  WAVE is the wavefront width.
+constexpr int LANES = 16;
+constexpr int WAVE = 64;
 
 // Device view of a mesh, passed by value to the launchers.
 struct MeshDev {
     int p = 0, np = 0, nq = 0, ne = 0;
     int n = 0;         // real elements
-    int npad = 0;      // padded to a multiple of 64
+    int npad = 0;      // padded to a multiple of 64 (whole workgroups)
     int nedge = 0;
     bool lanes4 = false;  // fused kernels: 4 lanes per element instead of 1
     // domain boundaries: per element 4 bits per side (0 interior, 1 wall,
@@ -44,7 +48,7 @@ struct MeshDev {
     double gamma = 1.4;
     const double* tab = nullptr;      // reference tables (TableLayout)
     const float* tab32 = nullptr;     // the same tables rounded to FP32 (mixed precision)
-    const double* geo = nullptr;      // [blk][6][64]: adj00 adj01 adj10 adj11 1/detJ r_in
+    const double* geo = nullptr;      // [blk][6][LANES]: adj00 adj01 adj10 adj11 1/detJ r_in
     const double* vtx = nullptr;      // [npad][6] vertices (internal order), setup only
     const int* perm = nullptr;        // internal -> user element id
     const int* edge_l = nullptr;      // [nedge] left element (internal id)
@@ -59,9 +63,9 @@ struct MeshDev {
     const int* ecol = nullptr;        // [3][nedge] left, right, sides (as edge_l/r/sd) in colour order
     const double* edge_gc = nullptr;  // [3][nedge] as edge_g, in colour order
     // per element side (element-wise surface integration), block-major:
-    const int* side_nb = nullptr;     // [blk][3][64] neighbour across side q (internal id)
-    const int* side_q = nullptr;      // [blk][64] neighbour's sides, 2 bits per side
-    const double* side_g = nullptr;   // [blk][9][64] outward unit normal x, y and half length per side
+    const int* side_nb = nullptr;     // [blk][3][LANES] neighbour across side q (internal id)
+    const int* side_q = nullptr;      // [blk][LANES] neighbour's sides, 2 bits per side
+    const double* side_g = nullptr;   // [blk][9][LANES] outward unit normal x, y and half length per side
 };
 
 // Fused step-length bookkeeping of the multi-step path (4-lane kernels):

@@ -2,10 +2,11 @@
 // equations, eq. (2ddg0) with the flux of eq. (euler).
 //
 // Data layout.  Modal coefficients are element-blocked structure of arrays:
-// C[blk][m][j][lane] with 64 elements (one wavefront) per block, so that a
-// wavefront reading mode j of variable m touches 512 contiguous bytes.  Edge
-// traces and per-side surface fluxes use the same blocking:
-// T[blk][q][k][m][lane] (side q of the element, edge point k).
+// C[blk][m][j][lane] with LANES = 16 elements per block, so that one (m, j)
+// row of a block is one 128-byte line: a one-lane wavefront reading mode j of
+// variable m touches four whole lines, and a neighbour gather touches one
+// line per row it needs.  Edge traces and per-side surface fluxes use the
+// same blocking: T[blk][q][k][m][lane] (side q of the element, edge point k).
 //
 // Kernels (one work-item per element or per edge, wave64):
 //   k_traces   U at the p+1 Gauss points of the three sides of each element
@@ -55,7 +56,7 @@ struct Ord {
 
 constexpr int BLOCK = 256;
 
-__device__ __forceinline__ int state_off(int e, int nfield) { return (e >> 6) * nfield * LANES + (e & 63); }
+__device__ __forceinline__ int state_off(int e, int nfield) { return (e / LANES) * nfield * LANES + (e % LANES); }
 
 // Reciprocal and square root for the flux arithmetic: the hardware
 // approximations (v_rcp, v_rsq) refined by one Newton step, a few
@@ -500,12 +501,12 @@ __device__ __forceinline__ double dt_local(double gamma, double rin, double c0r,
 __device__ __forceinline__ double block_min(double v, double* red)
 {
 #pragma unroll
-    for (int o = LANES / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    if ((threadIdx.x & (LANES - 1)) == 0) red[threadIdx.x / LANES] = v;
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
     __syncthreads();
     double r = red[0];
 #pragma unroll
-    for (int w = 1; w < BLOCK / LANES; ++w) r = fmin(r, red[w]);
+    for (int w = 1; w < BLOCK / WAVE; ++w) r = fmin(r, red[w]);
     __syncthreads();  // red may be reused
     return r;
 }
@@ -1217,7 +1218,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     // the FP32 form runs its contractions on the matrix cores (MFMA)
     constexpr bool MF = !F64 && DG_MIXED_MFMA;
     __shared__ T phs[3 * SS];
-    __shared__ double red[BLOCK / LANES];
+    __shared__ double red[BLOCK / WAVE];
     __shared__ Pair<T> xq[(BLOCK / 4) * XQUAD];
     __shared__ float mt[MF ? MTab<P>::SIZE : 1];
     if constexpr (MF) load_mfma_tables<P>((const float*)tab, mt);
