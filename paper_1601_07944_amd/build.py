@@ -22,6 +22,7 @@ SOURCES = [
     "dg_kernels_p3.hip",
     "dg_kernels_p4.hip",
     "dg_kernels_p5.hip",
+    "dg_kernels_f32.hip",
     "dg_kernels.hip",
     "dg_api.cpp",
     "dg_tables.cpp",
@@ -48,6 +49,13 @@ FLAGS = [
     "-packed-fp32-ops",
 ]
 
+# per-file additions: the one-lane FP32 stage kernels schedule their memory
+# instructions into clauses (measured faster there for p >= 2, not for p = 1 or
+# the other kernels)
+FILE_FLAGS = {
+    "dg_kernels_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"],
+}
+
 
 def _hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -59,7 +67,7 @@ def build(verbose: bool = False, extra=(), jobs: int | None = None) -> str:
 
     def compile_one(src):
         obj = os.path.join(OBJ, src + ".o")
-        cmd = [_hipcc(), *FLAGS, *extra, *inc, "-c", "-o", obj, os.path.join(CSRC, src)]
+        cmd = [_hipcc(), *FLAGS, *FILE_FLAGS.get(src, []), *extra, *inc, "-c", "-o", obj, os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
