@@ -117,13 +117,14 @@ def test_edge_count_with_boundaries():
     assert dm.info.n_edges == nb + (3 * mesh.n_elem - nb) // 2
 
 
-@pytest.mark.parametrize("kind", ["walls", "channel"])
-@pytest.mark.parametrize("p", [1, 3, 5])
-def test_mixed_rhs_within_bound(kind, p):
+@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("kind", ["walls", "channel", "state"])
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
+def test_mixed_rhs_within_bound(kind, p, lanes):
     mesh = box(kind)
-    orc, dm = pair(mesh, p, 0)
+    orc, dm = pair(mesh, p, lanes)
     C = orc.project(flow)
-    case(f"dg_rhs DG_MIXED box={kind} p={p}")
+    case(f"dg_rhs DG_MIXED box={kind} p={p} lanes={lanes}")
     got = dm.unpack(dm.rhs(dm.pack(dev(C)), prec=1)).cpu().numpy()
     assert rel_l2(got, orc.rhs(C)) <= 3e-5
 

@@ -64,7 +64,7 @@ def test_mixed_rhs_bound(p, lanes):
 
 
 @pytest.mark.parametrize("lanes", [1, 4])
-@pytest.mark.parametrize("p", [2, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_mixed_100_steps_smooth_unit_square(p, lanes):
     # smooth density wave on a periodic Delaunay mesh of the unit square
     import torch
