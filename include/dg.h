@@ -30,17 +30,29 @@
  * the caller (e.g. a torch tensor); the library never allocates in the calls
  * that take a stream.  Workspace sizes come from dg_mesh_info.  `stream` is
  * a hipStream_t passed as void* (NULL = the null stream).  All calls that
- * take a stream are asynchronous on it unless stated otherwise.  A mesh is
- * immutable after creation, so calls on different streams with separate
- * workspaces may overlap.  Results are deterministic: no atomics; every
- * output is written by exactly one work-item.
+ * take a stream are asynchronous on it unless stated otherwise.  The mesh's
+ * geometry and tables are immutable after creation, and the default
+ * (element-wise) kernels keep no per-call state in the mesh, so such calls
+ * on different streams with separate workspaces and outputs may overlap.
+ * Three things do keep per-call state in the mesh, and with them the calls
+ * on one mesh must come from one host thread at a time and, with the
+ * stream concurrency on, be queued on one stream at a time: the settings
+ * (dg_set_*), the two-stream edge-wise path (one side stream and one pair
+ * of fork/join events per mesh) and per-launch timing (one record list per
+ * mesh).  Results are deterministic: no atomics; every output is written by
+ * exactly one work-item.
+ * Sizes.  The kernels index per-element arrays with 32-bit offsets:
+ * dg_mesh_validate refuses (DG_EUNSUPPORTED) a mesh whose padded element
+ * count times max(4 N_p, 12 (p+1)) reaches 2^31, i.e. beyond about 44
+ * million triangles at p = 3 and 25 million at p = 5.
  *
  * Layouts.
  *   user layout     C[N][4][N_p], element order of dg_mesh_create, variables
  *                   (rho, rho u, rho v, E), modes in basis order;
  *   internal layout the library's own element-blocked order (elements
- *                   reordered along a space-filling curve, blocks of 64
- *                   elements, padded to a multiple of 64); state_len doubles.
+ *                   reordered along a Hilbert curve of the centroids,
+ *                   blocks of 16 elements [block][variable][mode][16],
+ *                   padded to a multiple of 64); state_len doubles.
  *   dg_pack / dg_unpack convert; dg_rhs, dg_max_dt and dg_rk_step work on
  *   the internal layout.
  *
@@ -131,11 +143,15 @@ int dg_mesh_destroy(dg_mesh m);
 int dg_mesh_info(dg_mesh m, dg_info* out);
 
 /* Physical coordinates of the volume quadrature points, xy_dev [N][n_vol_points][2]
- * (user element order), for evaluating initial data at them. */
+ * (user element order): the reference points of the degree-2p volume rule
+ * (Section "Volume Integration Kernel") mapped by eq. (2dmap), for
+ * evaluating initial data at them. */
 int dg_quad_points(dg_mesh m, double* xy_dev, void* stream);
 
-/* L2 projection onto the orthonormal basis (mass matrix det J * I):
- * c_j = sum_k w_k phi_j(r_k) u(x_k).  u_dev [N][n_vol_points][4] holds the
+/* L2 projection of initial data onto the orthonormal basis (Section
+ * "Outline of Algorithm" starts from projected initial coefficients; with the
+ * orthonormal basis of eq. (np) the mass matrix is det J * I):
+ * c_j = sum_k w_k phi_j(r_k) u(x_k) with the degree-2p volume rule.  u_dev [N][n_vol_points][4] holds the
  * conserved variables at dg_quad_points (user order); C_dev receives the
  * internal-layout state (padding zeroed). */
 int dg_project(dg_mesh m, const double* u_dev, double* C_dev, void* stream);
@@ -150,7 +166,10 @@ int dg_unpack(dg_mesh m, const double* C_dev, double* C_user_dev, void* stream);
  * surface mode, else DG_EUNSUPPORTED). */
 int dg_rhs(dg_mesh m, const double* C_dev, double* R_dev, dg_precision prec, void* ws_dev, void* stream);
 
-/* Stable time step (the paper computes one per step on the device): writes
+/* Stable time step (Section "Outline of Algorithm": a stable step length is
+ * computed on the device before every time step; the paper gives no formula,
+ * the library's is the CFL bound below with the element's inscribed radius
+ * and its mean wave speed |v| + c, cfl = 0.3/(2p+1) by convention): writes
  * dt = cfl * min_i r_i / (|v_i| + c_i) to dt_dev[0], or NaN when an element
  * mean is non-physical.  If dt_host is not NULL the call also copies the
  * value to *dt_host, waits for the stream, and returns DG_ENONPHYS for NaN.
@@ -158,7 +177,9 @@ int dg_rhs(dg_mesh m, const double* C_dev, double* R_dev, dg_precision prec, voi
 int dg_max_dt(dg_mesh m, const double* C_dev, double cfl, double* dt_dev, double* dt_host, void* ws_dev,
               void* stream);
 
-/* One SSP-RK3 step in place on the internal-layout state C_dev:
+/* One explicit Runge-Kutta time step (Section "Time-stepping": every stage
+ * evaluates the right-hand side of eq. (2ddg0) once) in place on the
+ * internal-layout state C_dev; by default the three-stage SSP scheme:
  *   u1 = u + dt L(u);  u2 = 3/4 u + 1/4 (u1 + dt L(u1));
  *   u  = 1/3 u + 2/3 (u2 + dt L(u2)).
  * The step length is dt_dev[0] when dt_dev is not NULL (e.g. the output of

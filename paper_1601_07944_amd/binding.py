@@ -191,6 +191,32 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def check_tensor(t, name, device, numel=None, min_numel=None, dtype="float64", min_bytes=None):
+    """Raise ValueError unless t is a contiguous torch tensor on `device`
+    with the given dtype ("float64", or None for any) and exactly `numel`
+    elements (or at least `min_numel` elements, or at least `min_bytes`
+    bytes).  Every entry point checks its tensors with this before any
+    launch: a kernel handed a host pointer, a tensor of another dtype or a
+    buffer that is too short would read or write outside it."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.device != device:
+        raise ValueError(f"{name}: tensor is on {t.device}, the mesh is on {device}")
+    if dtype is not None and t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{name}: dtype {t.dtype}, expected torch.{dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor is not contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected at least {min_numel}")
+    if min_bytes is not None and t.numel() * t.element_size() < min_bytes:
+        raise ValueError(f"{name}: {t.numel() * t.element_size()} bytes, expected at least {min_bytes}")
+    return t
+
+
 class DGMesh:
     """A mesh on the current device (dg_mesh_create); torch tensors carry
     all device memory.  States passed to rhs / rk_step / max_dt are in the
@@ -233,6 +259,16 @@ class DGMesh:
         except Exception:
             pass
 
+    # -- argument checks (before any launch) --------------------------------
+    def _state(self, t, name):
+        return check_tensor(t, name, self.device, numel=int(self.info.state_len))
+
+    def _ws_check(self, t, nbytes, name="ws"):
+        return check_tensor(t, name, self.device, dtype=None, min_bytes=int(nbytes))
+
+    def _dt(self, t, name="dt_dev", count=1):
+        return check_tensor(t, name, self.device, min_numel=count)
+
     # -- allocation helpers (torch owns device memory) --------------------
     def empty_state(self):
         import torch
@@ -256,28 +292,31 @@ class DGMesh:
         return xy
 
     def project(self, u, out=None, stream=None):
-        out = self.empty_state() if out is None else out
-        assert u.is_contiguous() and u.dtype.is_floating_point and u.numel() == self.n * self.nq * 4
+        out = self.empty_state() if out is None else self._state(out, "out")
+        check_tensor(u, "u", self.device, numel=self.n * self.nq * 4)
         _check(self._lib.dg_project(self._h, _ptr(u), _ptr(out), _stream(stream)))
         return out
 
     def pack(self, C_user, out=None, stream=None):
-        out = self.empty_state() if out is None else out
-        assert C_user.is_contiguous() and C_user.numel() == self.n * 4 * self.np
+        out = self.empty_state() if out is None else self._state(out, "out")
+        check_tensor(C_user, "C_user", self.device, numel=self.n * 4 * self.np)
         _check(self._lib.dg_pack(self._h, _ptr(C_user), _ptr(out), _stream(stream)))
         return out
 
     def unpack(self, C, out=None, stream=None):
         import torch
 
+        self._state(C, "C")
         if out is None:
             out = torch.empty((self.n, 4, self.np), dtype=torch.float64, device=self.device)
+        check_tensor(out, "out", self.device, numel=self.n * 4 * self.np)
         _check(self._lib.dg_unpack(self._h, _ptr(C), _ptr(out), _stream(stream)))
         return out
 
     def rhs(self, C, out=None, prec=DG_FP64, ws=None, stream=None):
-        out = self.empty_state() if out is None else out
-        ws = self.workspace("rhs") if ws is None else ws
+        self._state(C, "C")
+        out = self.empty_state() if out is None else self._state(out, "out")
+        ws = self.workspace("rhs") if ws is None else self._ws_check(ws, self.info.ws_rhs)
         _check(self._lib.dg_rhs(self._h, _ptr(C), _ptr(out), prec, _ptr(ws), _stream(stream)))
         return out
 
@@ -285,8 +324,9 @@ class DGMesh:
         """Returns (dt_dev tensor, host float or None)."""
         import torch
 
-        dt_dev = torch.empty(1, dtype=torch.float64, device=self.device) if dt_dev is None else dt_dev
-        ws = self.workspace("rhs") if ws is None else ws
+        self._state(C, "C")
+        dt_dev = torch.empty(1, dtype=torch.float64, device=self.device) if dt_dev is None else self._dt(dt_dev)
+        ws = self.workspace("rhs") if ws is None else self._ws_check(ws, self.info.ws_rhs)
         host = ctypes.c_double(0.0)
         _check(self._lib.dg_max_dt(self._h, _ptr(C), float(cfl), _ptr(dt_dev),
                                    ctypes.byref(host) if to_host else None, _ptr(ws), _stream(stream)))
@@ -330,6 +370,7 @@ class DGMesh:
 
     def limit(self, C, stream=None):
         """Barth-Jespersen limiter (p = 1) applied once, in place; returns C."""
+        self._state(C, "C")
         _check(self._lib.dg_limit(self._h, _ptr(C), _stream(stream)))
         return C
 
@@ -348,19 +389,31 @@ class DGMesh:
         """nsteps SSP-RK3 steps with the device CFL step length (in place)."""
         import torch
 
-        dt_dev = torch.empty(1, dtype=torch.float64, device=self.device) if dt_dev is None else dt_dev
-        ws = self.workspace("step") if ws is None else ws
+        if int(nsteps) < 0:
+            raise ValueError(f"nsteps = {nsteps} < 0")
+        self._state(C, "C")
+        dt_dev = torch.empty(1, dtype=torch.float64, device=self.device) if dt_dev is None else self._dt(dt_dev)
+        if dt_hist is not None:
+            self._dt(dt_hist, "dt_hist", max(1, int(nsteps)))
+        ws = self.workspace("step") if ws is None else self._ws_check(ws, self.info.ws_step)
         _check(self._lib.dg_advance(self._h, _ptr(C), int(nsteps), float(cfl), _ptr(dt_dev),
                                     _ptr(dt_hist) if dt_hist is not None else None, prec, _ptr(ws), _stream(stream)))
         return dt_dev
 
     def rhs_vjp(self, C, Rbar, out=None, stream=None):
-        out = self.empty_state() if out is None else out
+        self._state(C, "C")
+        self._state(Rbar, "Rbar")
+        out = self.empty_state() if out is None else self._state(out, "out")
         _check(self._lib.dg_rhs_vjp(self._h, _ptr(C), _ptr(Rbar), _ptr(out), None, _stream(stream)))
         return out
 
     def rk_step_stages(self, C, u1, u2, dt=0.0, dt_dev=None, ws=None, stream=None):
-        ws = self.workspace("step") if ws is None else ws
+        self._state(C, "C")
+        self._state(u1, "u1")
+        self._state(u2, "u2")
+        if dt_dev is not None:
+            self._dt(dt_dev)
+        ws = self.workspace("step") if ws is None else self._ws_check(ws, self.info.ws_step)
         _check(self._lib.dg_rk_step_stages(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None,
                                            _ptr(u1), _ptr(u2), _ptr(ws), _stream(stream)))
         return C
@@ -368,11 +421,22 @@ class DGMesh:
     def rk_step_vjp(self, C, ubar, dt=0.0, dt_dev=None, u1=None, u2=None, out=None, ws=None, stream=None):
         import torch
 
-        out = self.empty_state() if out is None else out
+        self._state(C, "C")
+        self._state(ubar, "ubar")
+        if (u1 is None) != (u2 is None):
+            raise ValueError("pass both stage states u1 and u2, or neither")
+        if u1 is not None:
+            self._state(u1, "u1")
+            self._state(u2, "u2")
+        if dt_dev is not None:
+            self._dt(dt_dev)
+        out = self.empty_state() if out is None else self._state(out, "out")
         if ws is None:
             if getattr(self, "_ws_vjp", None) is None:
                 self._ws_vjp = torch.empty(self.info.ws_vjp, dtype=torch.uint8, device=self.device)
             ws = self._ws_vjp
+        else:
+            self._ws_check(ws, self.info.ws_vjp)
         _check(self._lib.dg_rk_step_vjp(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None,
                                         _ptr(u1) if u1 is not None else None, _ptr(u2) if u2 is not None else None,
                                         _ptr(ubar), _ptr(out), _ptr(ws), _stream(stream)))
@@ -381,7 +445,9 @@ class DGMesh:
     def eval_points(self, C, out=None, stream=None):
         import torch
 
+        self._state(C, "C")
         out = torch.empty((self.n, self.nq, 4), dtype=torch.float64, device=self.device) if out is None else out
+        check_tensor(out, "out", self.device, numel=self.n * self.nq * 4)
         _check(self._lib.dg_eval_points(self._h, _ptr(C), _ptr(out), _stream(stream)))
         return out
 
@@ -389,11 +455,15 @@ class DGMesh:
         import torch
 
         out = torch.empty((self.n, self.nq), dtype=torch.float64, device=self.device) if out is None else out
+        check_tensor(out, "out", self.device, numel=self.n * self.nq)
         _check(self._lib.dg_quad_weights(self._h, _ptr(out), _stream(stream)))
         return out
 
     def rk_step(self, C, dt=0.0, dt_dev=None, prec=DG_FP64, ws=None, stream=None):
-        ws = self.workspace("step") if ws is None else ws
+        self._state(C, "C")
+        if dt_dev is not None:
+            self._dt(dt_dev)
+        ws = self.workspace("step") if ws is None else self._ws_check(ws, self.info.ws_step)
         _check(self._lib.dg_rk_step(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None, prec,
                                     _ptr(ws), _stream(stream)))
         return C

@@ -6,6 +6,8 @@ into paper_1601_07944_amd/libdgmi.so.
 """
 from __future__ import annotations
 
+import hashlib
+import json
 import os
 import subprocess
 import sys
@@ -16,6 +18,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libdgmi.so")
+# written beside the library by build(): the hash of the sources and flags it
+# was compiled from
+STAMP = LIB + ".sources.json"
 SOURCES = [
     "dg_kernels_p1.hip",
     "dg_kernels_p2.hip",
@@ -61,9 +66,43 @@ def _hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
+def source_files():
+    """Every file the library is compiled from: the kernel and host sources
+    under csrc/ and the public header."""
+    files = sorted(
+        os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".hip", ".cpp"))
+    )
+    return files + [os.path.join(ROOT, "include", "dg.h")]
+
+
+def source_hash() -> str:
+    """sha256 (first 16 hex digits) of the library's sources and compiler
+    flags; build() records it beside libdgmi.so."""
+    h = hashlib.sha256()
+    for f in source_files():
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    h.update(json.dumps([FLAGS, FILE_FLAGS, SOURCES]).encode())
+    return h.hexdigest()[:16]
+
+
+def built_hash():
+    """The source hash libdgmi.so was built from, or None (no library, or
+    no record of its sources)."""
+    if not os.path.exists(LIB) or not os.path.exists(STAMP):
+        return None
+    try:
+        with open(STAMP) as f:
+            return json.load(f).get("source_sha256_16")
+    except (OSError, ValueError):
+        return None
+
+
 def build(verbose: bool = False, extra=(), jobs: int | None = None) -> str:
     os.makedirs(OBJ, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include")]
+    digest = source_hash()
 
     def compile_one(src):
         obj = os.path.join(OBJ, src + ".o")
@@ -83,15 +122,26 @@ def build(verbose: bool = False, extra=(), jobs: int | None = None) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
+    if os.path.exists(STAMP):
+        os.remove(STAMP)
     os.replace(tmp, LIB)
+    # extra flags make a library that no longer matches the plain sources
+    rec = {"source_sha256_16": digest if not extra else None, "extra_flags": list(extra)}
+    with open(STAMP, "w") as f:
+        json.dump(rec, f)
     return LIB
+
+
+def ensure_built() -> str:
+    """Build libdgmi.so unless the library present was built from exactly
+    the current sources and flags (the hash recorded beside it by build());
+    a library without that record, or from other sources, is rebuilt."""
+    if built_hash() == source_hash():
+        return LIB
+    print(f"[build] libdgmi.so missing or stale (sources {source_hash()}, built {built_hash()}): rebuilding",
+          file=sys.stderr, flush=True)
+    return build()
 
 
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv, extra=[a for a in sys.argv[1:] if a != "-v"]))
-
-
-def ensure_built() -> str:
-    """Build libdgmi.so only if there is none (tests, smoke and the benchmark
-    use whatever is built; build() always compiles)."""
-    return LIB if os.path.exists(LIB) else build()

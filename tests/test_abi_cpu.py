@@ -158,3 +158,122 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
             B.load(str(tmp_path / "libdgmi.so"))
     finally:
         B._lib = saved
+
+
+def test_validate_rejects_meshes_beyond_32bit_indexing():
+    # the kernels index per-element arrays with 32-bit offsets: a mesh whose
+    # largest padded field offset reaches 2^31 is refused before any array
+    # is read (so tiny placeholder arrays are enough here)
+    v = np.zeros((1, 3, 2))
+    nb = np.zeros((1, 3), dtype=np.int64)
+    ns = np.zeros((1, 3), dtype=np.int8)
+    lib = B.load()
+    for p in (1, 3, 5):
+        np_ = (p + 1) * (p + 2) // 2
+        per_elem = max(4 * np_, 12 * (p + 1))
+        n_bad = (2**31) // per_elem + 64
+        assert lib.dg_mesh_validate(p, n_bad, v.ctypes.data, nb.ctypes.data, ns.ctypes.data) == -4
+        assert "32-bit" in B.last_error()
+    # and an element count beyond int32 altogether
+    assert lib.dg_mesh_validate(1, 2**31 + 5, v.ctypes.data, nb.ctypes.data, ns.ctypes.data) == -4
+
+
+class _FakeMesh(B.DGMesh):
+    """A DGMesh whose argument checks can run without a GPU: no library
+    handle (any call that got past the checks would fail on it)."""
+
+    def __init__(self, n=10, p=2):
+        import torch
+
+        np_ = (p + 1) * (p + 2) // 2
+        npad = (n + 63) // 64 * 64
+        info = B.dg_info()
+        info.p, info.n_modes, info.n_vol_points, info.n_edge_points = p, np_, 6, p + 1
+        info.n_elem, info.n_elem_pad, info.state_len = n, npad, npad * 4 * np_
+        info.ws_rhs, info.ws_step, info.ws_vjp = 1000, 2000, 3000
+        self.info, self.p, self.n, self.np, self.nq = info, p, n, np_, 6
+        self.device = torch.device("cpu")
+        self._h = None
+        self._lib = None
+        self._ws = None
+
+    def close(self):
+        pass
+
+
+def test_binding_rejects_bad_tensors_before_any_launch():
+    import torch
+
+    dm = _FakeMesh()
+    good = torch.zeros(dm.info.state_len, dtype=torch.float64)
+    bad = [
+        ("float32", torch.zeros(dm.info.state_len, dtype=torch.float32)),
+        ("short", torch.zeros(dm.info.state_len - 1, dtype=torch.float64)),
+        ("user layout", torch.zeros(dm.n * 4 * dm.np, dtype=torch.float64)),
+        ("strided", torch.zeros(2 * dm.info.state_len, dtype=torch.float64)[::2]),
+        ("meta device", torch.zeros(dm.info.state_len, dtype=torch.float64, device="meta")),
+    ]
+    calls = [
+        lambda t: dm.rhs(t, out=good, ws=torch.zeros(1000, dtype=torch.uint8)),
+        lambda t: dm.rhs(good, out=t, ws=torch.zeros(1000, dtype=torch.uint8)),
+        lambda t: dm.rk_step(t, 0.1, ws=torch.zeros(2000, dtype=torch.uint8)),
+        lambda t: dm.advance(t, 3, 0.1, dt_dev=torch.zeros(1, dtype=torch.float64),
+                             ws=torch.zeros(2000, dtype=torch.uint8)),
+        lambda t: dm.max_dt(t, 0.1, dt_dev=torch.zeros(1, dtype=torch.float64),
+                            ws=torch.zeros(1000, dtype=torch.uint8)),
+        lambda t: dm.rhs_vjp(good, t, out=good),
+        lambda t: dm.rk_step_vjp(good, t, 0.1, out=good, ws=torch.zeros(3000, dtype=torch.uint8)),
+        lambda t: dm.rk_step_stages(good, t, good, 0.1, ws=torch.zeros(2000, dtype=torch.uint8)),
+        lambda t: dm.limit(t),
+        lambda t: dm.unpack(t),
+        lambda t: dm.eval_points(t),
+    ]
+    for call in calls:
+        for name, t in bad:
+            with pytest.raises(ValueError):
+                call(t)
+    # user-layout arguments and the small ones
+    with pytest.raises(ValueError):
+        dm.pack(torch.zeros(dm.n * 4 * dm.np, dtype=torch.float32), out=good)
+    with pytest.raises(ValueError):
+        dm.pack(torch.zeros(dm.n * 4 * dm.np + 1, dtype=torch.float64), out=good)
+    with pytest.raises(ValueError):
+        dm.project(torch.zeros(dm.n * dm.nq * 4, dtype=torch.float32), out=good)
+    with pytest.raises(ValueError):
+        dm.unpack(good, out=torch.zeros(dm.n * 4 * dm.np - 1, dtype=torch.float64))
+    with pytest.raises(ValueError):  # workspace too small
+        dm.rk_step(good, 0.1, ws=torch.zeros(1999, dtype=torch.uint8))
+    with pytest.raises(ValueError):  # a step-length history shorter than the steps
+        dm.advance(good, 3, 0.1, dt_dev=torch.zeros(1, dtype=torch.float64), dt_hist=torch.zeros(2, dtype=torch.float64),
+                   ws=torch.zeros(2000, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        dm.advance(good, -1, 0.1)
+    with pytest.raises(ValueError):  # one stage state without the other
+        dm.rk_step_vjp(good, good, 0.1, u1=good, out=good, ws=torch.zeros(3000, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        B.check_tensor(np.zeros(3), "x", torch.device("cpu"))
+
+
+def test_stale_library_is_detected(monkeypatch, tmp_path):
+    # ensure_built() rebuilds unless the library was built from exactly the
+    # current sources: the recorded hash is compared, not file times
+    from paper_1601_07944_amd import build as Bd
+
+    lib = tmp_path / "libdgmi.so"
+    stamp = tmp_path / "libdgmi.so.sources.json"
+    lib.write_bytes(b"")
+    monkeypatch.setattr(Bd, "LIB", str(lib))
+    monkeypatch.setattr(Bd, "STAMP", str(stamp))
+    calls = []
+    monkeypatch.setattr(Bd, "build", lambda *a, **k: calls.append(1) or str(lib))
+    assert Bd.built_hash() is None
+    Bd.ensure_built()  # no record of its sources
+    assert calls == [1]
+    stamp.write_text('{"source_sha256_16": "0000000000000000"}')
+    Bd.ensure_built()  # built from other sources
+    assert calls == [1, 1]
+    stamp.write_text('{"source_sha256_16": "%s"}' % Bd.source_hash())
+    Bd.ensure_built()  # current
+    assert calls == [1, 1]
+    assert len(Bd.source_hash()) == 16
+    assert any(f.endswith("dg_kernels.h") for f in Bd.source_files())

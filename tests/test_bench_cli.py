@@ -15,7 +15,8 @@ def run(*args):
 def test_help_lists_the_options():
     r = run("--help")
     assert r.returncode == 0, r.stderr
-    for opt in ("--gpus", "--steps", "--warmup", "--counter-pass", "--counter-prec", "--workload", "--surface-variants"):
+    for opt in ("--gpus", "--steps", "--warmup", "--counter-pass", "--counter-prec", "--counter-workload", "--quick",
+                "--sweep-steps"):
         assert opt in r.stdout
 
 
