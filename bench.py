@@ -186,24 +186,28 @@ def advance_throughput(dm, C0, p, prec, steps, warmup, split_steps=10):
     kt = dm.timing_read()
     del Cs
     st_ms, st_n = kt["stage"]
-    assert st_n == 3 * split_steps, kt
-    dt_per_step = kt["dt"][0] / split_steps  # separate reductions (none when fused into the stages)
-    launch_ms = (ms - dt_per_step) / 3.0
     dof = dm.n * dm.np * 4
-    ach = algorithmic_bytes_stage_kernel(dm.n, dm.np, 2.0 / 3.0) / (launch_ms * 1e-3) / 1e9
     out = {
         "value": dof * 3 / (ms * 1e-3),
         "ms_per_step": ms,
-        "stage_launch_us": launch_ms * 1e3,
-        "stage_launch_us_with_event_pairs": st_ms / st_n * 1e3,
-        "dt_reduction_us_per_step": dt_per_step * 1e3,
         "ms_per_step_with_kernel_events": ms_split,
-        "stage_hbm_GBs_algorithmic": ach,
-        "frac_hbm": ach / HBM_PEAK_GBS,
         "wall_s_timed_region": wall,
         "lanes_per_element": auto_lanes(dm.n, p),
         "precision": "fp64" if prec == B.DG_FP64 else "mixed",
+        "kernel_ms_per_step": {k: v[0] / split_steps for k, v in kt.items() if v[1]},
     }
+    if st_n == 3 * split_steps:
+        # the fused stage kernels: one launch per RK stage
+        dt_per_step = kt["dt"][0] / split_steps  # separate reductions (none when fused into the stages)
+        launch_ms = (ms - dt_per_step) / 3.0
+        ach = algorithmic_bytes_stage_kernel(dm.n, dm.np, 2.0 / 3.0) / (launch_ms * 1e-3) / 1e9
+        out.update({
+            "stage_launch_us": launch_ms * 1e3,
+            "stage_launch_us_with_event_pairs": st_ms / st_n * 1e3,
+            "dt_reduction_us_per_step": dt_per_step * 1e3,
+            "stage_hbm_GBs_algorithmic": ach,
+            "frac_hbm": ach / HBM_PEAK_GBS,
+        })
     return out, C
 
 
@@ -484,8 +488,9 @@ def cache_resident(steps, dev):
 
 
 def counter_pass(args):
-    """For rocprofv3 --pmc runs: a few steps of the headline workload (or
-    the cache-resident one), then a 256 MiB device copy of known size, the
+    """For rocprofv3 --pmc runs: --steps steps of the headline workload (or
+    the cache-resident one) for every order in --p and every precision in
+    --counter-prec, then a 256 MiB device copy of known size, the
     calibration kernel for FETCH_SIZE / WRITE_SIZE."""
     import torch
 
@@ -493,21 +498,30 @@ def counter_pass(args):
     from paper_1601_07944_amd import workloads as W
 
     dev = torch.device("cuda", 0)
-    p = args.p
     if args.counter_workload == "cache_resident":
         mesh, init = W.square_mesh(128, 10.0, 0.2, 1), W.isentropic_vortex
     else:
         mesh, init = W.delaunay_mesh(TARGET_POINTS, TARGET_SEED), W.density_jump
-    dm = B.DGMesh.from_mesh(mesh, p)
-    C = make_state(dm, init, dev)
-    prec = B.DG_MIXED if args.counter_prec == "mixed" else B.DG_FP64
     dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
-    dm.advance(C, args.steps, 0.3 / (2 * p + 1), dt_dev=dt_dev, prec=prec)
+    for p in [int(x) for x in str(args.p).split(",")]:
+        dm = B.DGMesh.from_mesh(mesh, p)
+        C0 = make_state(dm, init, dev)
+        for name in args.counter_prec.split(","):
+            prec = B.DG_MIXED if name == "mixed" else B.DG_FP64
+            C = C0.clone()
+            dm.advance(C, args.steps, 0.3 / (2 * p + 1), dt_dev=dt_dev, prec=prec)
+            torch.cuda.synchronize()
+            log(f"counter pass: p={p} {name} {args.steps} steps")
+            del C
+        dm.close()
+        del C0, dm
+        torch.cuda.empty_cache()
     a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)  # 256 MiB
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"counter_pass": True, "p": p, "n_elem": dm.n, "steps": args.steps, "copy_bytes": a.numel() * 8,
+    print(json.dumps({"counter_pass": True, "p": args.p, "prec": args.counter_prec, "n_elem": mesh.n_elem,
+                      "steps": args.steps, "copy_bytes": a.numel() * 8,
                       "stage_source_sha256_16": stage_source_digest()}), flush=True)
 
 
@@ -534,9 +548,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline, mixed and rhs_only only")
     ap.add_argument("--counter-pass", action="store_true",
                     help="for rocprofv3 --pmc runs: --steps steps, then a 256 MiB copy; prints nothing else")
-    ap.add_argument("--counter-prec", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--counter-prec", default="fp64", help="fp64, mixed or both (comma-separated)")
     ap.add_argument("--counter-workload", choices=["target", "cache_resident"], default="target")
-    ap.add_argument("--p", type=int, default=3, help="order of the counter pass")
+    ap.add_argument("--p", default="3", help="orders of the counter pass (comma-separated)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X; a multi-GPU run "

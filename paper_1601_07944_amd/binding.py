@@ -98,6 +98,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it first (python -m paper_1601_07944_amd.build)")
+    # torch first: it must bring up the HIP runtime before the library's
+    # code objects are registered with it
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     i32, i64 = ctypes.c_int, ctypes.c_int64
     lib.dg_last_error.restype = ctypes.c_char_p

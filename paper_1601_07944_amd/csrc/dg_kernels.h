@@ -584,6 +584,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
     constexpr int NP = O::NP, NQ = O::NQ, NE = O::NE;
     constexpr int SS = (NE * NP) | 1;
     __shared__ T phs[3 * SS];
+    __shared__ T urs[2 * NE * 4 * BLOCK];  // neighbours' traces of sides 1 and 2, [side-1][k][m][lane]
     for (int i = threadIdx.x; i < 3 * NE * NP; i += BLOCK) phs[(i / (NE * NP)) * SS + i % (NE * NP)] = tab[O::PHS + i];
     __syncthreads();
 
@@ -616,22 +617,23 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
 #pragma unroll
         for (int j = 0; j < NP; ++j) acc[m][j] = T(0);
 
-    // surface integral, eq. (surface): the element's own three sides
+    // surface integral, eq. (surface), over the element's three sides.  The
+    // neighbours' traces of all three sides are evaluated first, right after
+    // the element's own coefficients are read: the elements of a workgroup
+    // are mostly each other's neighbours, and their coefficients are then
+    // still in the caches (a side gathered later in the kernel's life finds
+    // them evicted on large meshes).  Sides 1 and 2 wait in LDS rows private
+    // to the lane, side 0 (gathered last) stays in registers.
     const int sides = sside[state_off(e, 1)];
     const int bcv = BC ? sbc[state_off(e, 1)] : 0;
     T G[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) G[m] = BC ? T(bcs[m]) : T(0);
-#pragma unroll 1
-    for (int q = 0; q < 3; ++q) {
+
+    // the neighbour's trace at its side qn, at the reversed edge points
+    auto gather = [&](int q, T (&UR)[NE][4]) {
         const int nb = snb[state_off(e, 3) + q * LANES];
         const int qn = (sides >> (2 * q)) & 3;
-        const int bc = (bcv >> (4 * q)) & 15;
-        const int go = state_off(e, 9) + 3 * q * LANES;
-        const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
-        const double hl = sgeo[go + 2 * LANES];
-        // neighbour trace at its side qn, at the reversed edge points
-        T UR[NE][4];
 #pragma unroll
         for (int k = 0; k < NE; ++k)
 #pragma unroll
@@ -650,6 +652,13 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
                 for (int m = 0; m < 4; ++m) UR[k][m] = fma(t, cv[m], UR[k][m]);
             }
         }
+    };
+    // one side: own trace, numerical flux, lift
+    auto side = [&](int q, T (&UR)[NE][4]) {
+        const int bc = (bcv >> (4 * q)) & 15;
+        const int go = state_off(e, 9) + 3 * q * LANES;
+        const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
+        const double hl = sgeo[go + 2 * LANES];
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
             const T* tl = tab + O::PHS + (q * NE + k) * NP;
@@ -675,6 +684,30 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
 #pragma unroll
                 for (int j = 1; j < NP; ++j) acc[m][j] = fma(tl[j], F[m], acc[m][j]);
         }
+    };
+
+    // (sides 1 and 2 first: gathering side 0 last keeps the fewest values
+    // live across the gathers)
+#pragma unroll
+    for (int q = 1; q < 3; ++q) {
+        T URq[NE][4];
+        gather(q, URq);
+#pragma unroll
+        for (int k = 0; k < NE; ++k)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) urs[(((q - 1) * NE + k) * 4 + m) * BLOCK + threadIdx.x] = URq[k][m];
+    }
+    T UR0[NE][4];
+    gather(0, UR0);
+    side(0, UR0);
+#pragma unroll 1
+    for (int q = 1; q < 3; ++q) {
+        T UR[NE][4];
+#pragma unroll
+        for (int k = 0; k < NE; ++k)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) UR[k][m] = urs[(((q - 1) * NE + k) * 4 + m) * BLOCK + threadIdx.x];
+        side(q, UR);
     }
 
     // volume integral, eq. (volume); grad phi_0 = 0, so modes j >= 1 only
