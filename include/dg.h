@@ -188,6 +188,31 @@ int dg_max_dt(dg_mesh m, const double* C_dev, double cfl, double* dt_dev, double
 int dg_rk_step(dg_mesh m, double* C_dev, double dt, const double* dt_dev, dg_precision prec, void* ws_dev,
                void* stream);
 
+/* Bytes of the library's static device scratch used by dg_rk_step_noalloc
+ * (64 MiB; every GPU the library runs on holds one copy until the process
+ * ends). */
+#define DG_NOALLOC_SCRATCH_BYTES (64LL << 20)
+
+/* dg_rk_step without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same launches and results, bit for bit, as
+ * dg_rk_step with the element-wise surface mode, with the stage states kept
+ * in the library's static scratch of the mesh's device instead of ws_dev.
+ * The call allocates nothing (no hipMalloc, no events, no per-launch
+ * timing).  C_dev, dt, dt_dev, prec and stream as for dg_rk_step.
+ * Limits and errors:
+ *   - the stage states, 2 x state_len x 8 bytes (3 x with the RK4
+ *     integrator), must fit DG_NOALLOC_SCRATCH_BYTES, else DG_EUNSUPPORTED
+ *     (e.g. up to 104,832 triangles at p = 3 with SSP-RK3);
+ *   - the surface mode must be the element-wise one (DG_EUNSUPPORTED);
+ *   - the mesh's device must be the current device (DG_EINVAL).
+ * Concurrency: every call on one GPU shares that GPU's scratch, and the
+ * scratch keeps the last call's stage states; calls that overlap on one GPU
+ * (different streams or host threads without ordering between them) race.
+ * Every value a call reads from the scratch it has written itself first, so
+ * nothing needs clearing between calls. */
+int dg_rk_step_noalloc(dg_mesh m, double* C_dev, double dt, const double* dt_dev, dg_precision prec, void* stream);
+
 /* nsteps SSP-RK3 steps in place, each with its own CFL step length taken
  * from the state at the start of the step (the paper's host-directed time
  * loop, Section "Time-stepping", kept on the device): the same results, bit

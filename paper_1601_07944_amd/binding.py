@@ -43,6 +43,7 @@ EXPORTS = [
     "dg_rhs",
     "dg_max_dt",
     "dg_rk_step",
+    "dg_rk_step_noalloc",
     "dg_advance",
     "dg_rhs_vjp",
     "dg_rk_step_vjp",
@@ -116,6 +117,7 @@ def load(path: str = LIB_PATH):
     lib.dg_rhs.argtypes = [_vp, _vp, _vp, i32, _vp, _vp]
     lib.dg_max_dt.argtypes = [_vp, _vp, ctypes.c_double, _vp, _dp, _vp, _vp]
     lib.dg_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _vp, i32, _vp, _vp]
+    lib.dg_rk_step_noalloc.argtypes = [_vp, _vp, ctypes.c_double, _vp, i32, _vp]
     lib.dg_advance.argtypes = [_vp, _vp, i64, ctypes.c_double, _vp, _vp, i32, _vp, _vp]
     lib.dg_rhs_vjp.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.dg_rk_step_vjp.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -470,4 +472,14 @@ class DGMesh:
         ws = self.workspace("step") if ws is None else self._ws_check(ws, self.info.ws_step)
         _check(self._lib.dg_rk_step(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None, prec,
                                     _ptr(ws), _stream(stream)))
+        return C
+
+    def rk_step_noalloc(self, C, dt=0.0, dt_dev=None, prec=DG_FP64, stream=None):
+        """dg_rk_step_noalloc: one step with the stage states in the
+        library's static device scratch (no workspace, nothing allocated)."""
+        self._state(C, "C")
+        if dt_dev is not None:
+            self._dt(dt_dev)
+        _check(self._lib.dg_rk_step_noalloc(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None,
+                                            prec, _stream(stream)))
         return C

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -17,6 +18,7 @@
 
 struct dg_mesh_s {
     dgk::MeshDev dev;
+    int device = 0;  // the HIP device the mesh was created on
     dgh::TableLayout lay;
     int64_t ws_rhs = 0, ws_step = 0, ws_vjp = 0;
     // workspace offsets (bytes)
@@ -99,6 +101,43 @@ uint64_t hilbert_key(uint64_t x, uint64_t y)
         }
     }
     return d;
+}
+
+}  // namespace
+
+// Scratch memory of dg_rk_step_noalloc: the stage states of one step, in a
+// device array that every GPU the library runs on holds until the process
+// ends (one copy per device, at its own address).  In host code `scratch`
+// only names the symbol; its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current (at the first
+// dg_mesh_create on it) and kept in g_scratch_ptr.
+static __device__ __align__(256) char scratch[DG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Looks up (once) the device address of `scratch` on device `dev`, which
+// must be the current device.
+int scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(DG_EUNSUPPORTED, "device %d: at most %d devices", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return DG_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(DG_EHIP, "hipGetSymbolAddress(scratch) gave a null address");
+    g_scratch_ptr[dev] = ptr;
+    return DG_OK;
+}
+
+void* scratch_ptr(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return dev >= 0 && dev < MAX_DEVICES ? g_scratch_ptr[dev] : nullptr;
 }
 
 }  // namespace
@@ -328,7 +367,11 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     if (!dgk::table_offset_check(p, lay) || lay.nq != nq)
         return fail(DG_EUNSUPPORTED, "internal error: table layout mismatch at p=%d", p);
 
+    int device = 0;
+    if (hipError_t e = hipGetDevice(&device); e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((rc = scratch_setup(device)) != DG_OK) return rc;
     dg_mesh m = new dg_mesh_s();
+    m->device = device;
     auto upload = [&](const void* src, size_t bytes, void** dst) -> int {
         void* d = nullptr;
         hipError_t e = hipMalloc(&d, std::max<size_t>(bytes, 256));
@@ -598,6 +641,72 @@ static void limit_stage(dg_mesh m, double* U, hipStream_t s)
     if (m->limiter == DG_LIMITER_BJ) timed(m, DG_KERNEL_LIMIT, s, [&] { dgk::launch_limit(m->dev, U, s); });
 }
 
+// The element-wise step (SSP-RK3, or the classic RK2 / RK4) with its stage
+// states at u1, u2 and, for RK4, the running sum at acc.  With `timing`
+// false no launch is bracketed by events (the allocation-free entry point
+// creates none).
+static void rk_step_elementwise(dg_mesh m, double* C, double dt, const double* dt_dev, bool mx, double* u1,
+                                double* u2, double* acc, hipStream_t s, bool timing)
+{
+    const dgk::MeshDev& d = m->dev;
+    auto run = [&](int kind, auto&& launch) {
+        if (timing)
+            timed(m, kind, s, launch);
+        else
+            launch();
+    };
+    auto limit = [&](double* U) {
+        if (m->limiter == DG_LIMITER_BJ) run(DG_KERNEL_LIMIT, [&] { dgk::launch_limit(d, U, s); });
+    };
+    if (m->integrator == DG_RK2) {
+        // Heun: u1 = u + dt L(u);  u = 1/2 u + 1/2 (u1 + dt L(u1))
+        dgk::StageGen g2;
+        g2.a = 0.5;
+        g2.b = 0.5;
+        g2.g = 0.5;  // X = the output (stage-0) state itself
+        run(DG_KERNEL_STAGE, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, dt, dt_dev, s); });
+        limit(u1);
+        run(DG_KERNEL_STAGE, [&] { dgk::launch_stage_general(d, mx, u1, C, dt, dt_dev, g2, s); });
+        limit(C);
+        return;
+    }
+    if (m->integrator == DG_RK4) {
+        // classic RK4 with the running sum S = u + dt (k1 + 2 k2 + 2 k3) / 6
+        dgk::StageGen g;
+        g.b = 1.0;
+        g.g = 0.5;
+        g.S = acc;
+        g.d = 1.0 / 6.0;
+        g.s_init = 1;  // u1 = u + dt/2 k1, S = u + dt/6 k1
+        run(DG_KERNEL_STAGE, [&] { dgk::launch_stage_general(d, mx, C, u1, dt, dt_dev, g, s); });
+        limit(u1);
+        g = dgk::StageGen();
+        g.a = 1.0;
+        g.X = C;
+        g.g = 0.5;
+        g.S = acc;
+        g.d = 1.0 / 3.0;  // u2 = u + dt/2 k2, S += dt/3 k2
+        run(DG_KERNEL_STAGE, [&] { dgk::launch_stage_general(d, mx, u1, u2, dt, dt_dev, g, s); });
+        limit(u2);
+        g.g = 1.0;  // u3 = u + dt k3, S += dt/3 k3 (u3 reuses u1)
+        run(DG_KERNEL_STAGE, [&] { dgk::launch_stage_general(d, mx, u2, u1, dt, dt_dev, g, s); });
+        limit(u1);
+        g = dgk::StageGen();
+        g.a = 1.0;
+        g.X = acc;
+        g.g = 1.0 / 6.0;  // u = S + dt/6 k4
+        run(DG_KERNEL_STAGE, [&] { dgk::launch_stage_general(d, mx, u1, C, dt, dt_dev, g, s); });
+        limit(C);
+        return;
+    }
+    run(DG_KERNEL_STAGE, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, dt, dt_dev, s); });
+    limit(u1);
+    run(DG_KERNEL_STAGE, [&] { dgk::launch_stage(d, 2, mx, u1, C, u2, dt, dt_dev, s); });
+    limit(u2);
+    run(DG_KERNEL_STAGE, [&] { dgk::launch_stage(d, 3, mx, u2, nullptr, C, dt, dt_dev, s); });
+    limit(C);
+}
+
 int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precision prec, void* ws, void* stream)
 {
     if (!m || !C || !ws) return fail(DG_EINVAL, "null argument");
@@ -616,58 +725,8 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
         return fail(DG_EUNSUPPORTED, "the limiter needs the element-wise surface mode");
     if (m->integrator != DG_RK_SSP3 && m->surface != DG_SURFACE_ELEMENTWISE)
         return fail(DG_EUNSUPPORTED, "RK2 / RK4 need the element-wise surface mode");
-    if (m->integrator == DG_RK2) {
-        // Heun: u1 = u + dt L(u);  u = 1/2 u + 1/2 (u1 + dt L(u1))
-        const bool mx = prec == DG_MIXED;
-        dgk::StageGen g2;
-        g2.a = 0.5;
-        g2.b = 0.5;
-        g2.g = 0.5;  // X = the output (stage-0) state itself
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, dt, dt_dev, s); });
-        limit_stage(m, u1, s);
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, u1, C, dt, dt_dev, g2, s); });
-        limit_stage(m, C, s);
-        return check_launch("dg_rk_step");
-    }
-    if (m->integrator == DG_RK4) {
-        // classic RK4 with the running sum S = u + dt (k1 + 2 k2 + 2 k3) / 6
-        const bool mx = prec == DG_MIXED;
-        double* S4 = (double*)(w + m->off_acc);
-        dgk::StageGen g;
-        g.b = 1.0;
-        g.g = 0.5;
-        g.S = S4;
-        g.d = 1.0 / 6.0;
-        g.s_init = 1;  // u1 = u + dt/2 k1, S = u + dt/6 k1
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, C, u1, dt, dt_dev, g, s); });
-        limit_stage(m, u1, s);
-        g = dgk::StageGen();
-        g.a = 1.0;
-        g.X = C;
-        g.g = 0.5;
-        g.S = S4;
-        g.d = 1.0 / 3.0;  // u2 = u + dt/2 k2, S += dt/3 k2
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, u1, u2, dt, dt_dev, g, s); });
-        limit_stage(m, u2, s);
-        g.g = 1.0;  // u3 = u + dt k3, S += dt/3 k3 (u3 reuses u1)
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, u2, u1, dt, dt_dev, g, s); });
-        limit_stage(m, u1, s);
-        g = dgk::StageGen();
-        g.a = 1.0;
-        g.X = S4;
-        g.g = 1.0 / 6.0;  // u = S + dt/6 k4
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, mx, u1, C, dt, dt_dev, g, s); });
-        limit_stage(m, C, s);
-        return check_launch("dg_rk_step");
-    }
     if (m->surface == DG_SURFACE_ELEMENTWISE) {
-        const bool mx = prec == DG_MIXED;
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, mx, C, nullptr, u1, dt, dt_dev, s); });
-        limit_stage(m, u1, s);
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, mx, u1, C, u2, dt, dt_dev, s); });
-        limit_stage(m, u2, s);
-        timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 3, mx, u2, nullptr, C, dt, dt_dev, s); });
-        limit_stage(m, C, s);
+        rk_step_elementwise(m, C, dt, dt_dev, prec == DG_MIXED, u1, u2, (double*)(w + m->off_acc), s, true);
         return check_launch("dg_rk_step");
     }
     if (m->surface == DG_SURFACE_COLOURED) {
@@ -710,6 +769,30 @@ int dg_rk_step(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precisi
     timed(m, DG_KERNEL_EDGE, s, [&] { dgk::launch_edge_flux(d, T0, S, s); });
     timed(m, DG_KERNEL_ELEMENT, s, [&] { dgk::launch_element(d, 3, u2, C, C, S, dt, dt_dev, nullptr, s); });
     return check_launch("dg_rk_step");
+}
+
+int dg_rk_step_noalloc(dg_mesh m, double* C, double dt, const double* dt_dev, dg_precision prec, void* stream)
+{
+    if (!m || !C) return fail(DG_EINVAL, "null argument");
+    if (prec != DG_FP64 && prec != DG_MIXED) return fail(DG_EINVAL, "unknown precision %d", prec);
+    if (m->surface != DG_SURFACE_ELEMENTWISE)
+        return fail(DG_EUNSUPPORTED, "dg_rk_step_noalloc runs the element-wise surface mode only");
+    // scratch layout: u1, u2 and, for RK4, the running sum
+    const size_t need = (m->integrator == DG_RK4 ? 3 : 2) * m->state_bytes;
+    if (need > (size_t)DG_NOALLOC_SCRATCH_BYTES)
+        return fail(DG_EUNSUPPORTED,
+                    "dg_rk_step_noalloc: this mesh needs %zu bytes of stage states, the static scratch holds %zu "
+                    "(use dg_rk_step with a workspace)",
+                    need, (size_t)DG_NOALLOC_SCRATCH_BYTES);
+    int dev = -1;
+    if (hipError_t e = hipGetDevice(&dev); e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != m->device)
+        return fail(DG_EINVAL, "the mesh lives on device %d but device %d is current", m->device, dev);
+    char* w = (char*)scratch_ptr(dev);
+    if (!w) return fail(DG_EHIP, "no scratch address for device %d", dev);
+    rk_step_elementwise(m, C, dt, dt_dev, prec == DG_MIXED, (double*)w, (double*)(w + m->state_bytes),
+                        (double*)(w + 2 * m->state_bytes), (hipStream_t)stream, false);
+    return check_launch("dg_rk_step_noalloc");
 }
 
 int dg_rhs_vjp(dg_mesh m, const double* C, const double* Rb, double* Cb, void* ws, void* stream)
