@@ -372,8 +372,11 @@ int dg_limit(dg_mesh m, double* C_dev, void* stream);
  * lane, at the price of more instructions per element: they pay off on
  * meshes too small to fill the GPU, and at p >= 4, where one lane's
  * registers cannot hold an element.  0 = automatic (4 lanes up to
- * DG_LANES4_MAX_ELEMENTS elements or for p >= 4, else 1).  Both give the
- * same result to rounding.  Returns DG_EINVAL for any other value. */
+ * DG_LANES4_MAX_ELEMENTS elements or for p >= 4, else 1; the adjoint
+ * kernels of dg_rhs_vjp and dg_rk_step_vjp take 4 lanes from p = 3 on at
+ * any size, where the one-lane adjoint holds too many values).  1 and 4
+ * apply to both.  Both give the same result to rounding.  Returns DG_EINVAL
+ * for any other value. */
 #define DG_LANES4_MAX_ELEMENTS 1048576
 int dg_set_lanes_per_element(dg_mesh m, int lanes);
 

@@ -416,6 +416,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     for (int c = 0; c <= ncolour; ++c) d.colour_off[c] = colour_off[c];
     d.gamma = gamma;
     d.lanes4 = N <= DG_LANES4_MAX_ELEMENTS || p >= 4;
+    d.vjp_lanes4 = d.lanes4 || p >= 3;
     d.tab = (const double*)d_tab;
     d.tab32 = (const float*)d_tab32;
     d.geo = (const double*)d_geo;
@@ -930,6 +931,7 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes)
     if (!m) return fail(DG_EINVAL, "null mesh");
     if (lanes != 0 && lanes != 1 && lanes != 4) return fail(DG_EINVAL, "lanes per element must be 0, 1 or 4");
     m->dev.lanes4 = lanes == 4 || (lanes == 0 && (m->dev.n <= DG_LANES4_MAX_ELEMENTS || m->dev.p >= 4));
+    m->dev.vjp_lanes4 = lanes == 4 || (lanes == 0 && (m->dev.lanes4 || m->dev.p >= 3));
     return ok();
 }
 

@@ -40,6 +40,7 @@ struct MeshDev {
     int npad = 0;      // padded to a multiple of 64 (whole workgroups)
     int nedge = 0;
     bool lanes4 = false;  // fused kernels: 4 lanes per element instead of 1
+    bool vjp_lanes4 = true;  // adjoint kernels: 4 lanes per element instead of 1
     // domain boundaries: per element 4 bits per side (0 interior, 1 wall,
     // 2 outflow, 3 prescribed state), and the prescribed state (4 doubles)
     const int* side_bc = nullptr;

