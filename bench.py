@@ -265,6 +265,22 @@ def adjoint_ratio(dm, C0, dt, nsteps, every):
     }
 
 
+def stream_copy(nbytes=2 << 30, reps=5):
+    """Device-to-device copy of nbytes (torch's copy kernel), HIP events over
+    reps copies: bytes read + written per second, the practical HBM ceiling
+    beside the 8 TB/s peak."""
+    import torch
+
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    tm = Timer()
+    ms = tm(lambda: [b.copy_(a) for _ in range(reps)]) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_moved": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(mesh, p, init, dof, n_all=3):
     """The oracle's right-hand side of the same mesh and state: n_all calls
     on every host core this process may use, then one call on one core."""
@@ -612,6 +628,7 @@ def main():
 
     launch_ms = head["stage_launch_us"] * 1e-3
     ach = head["stage_hbm_GBs_algorithmic"]
+    log("stream copy ...")
     tkey = f"stage_p3_delaunay4m_{'lanes4' if auto_lanes(dm.n, p) == 4 else 'lanes1'}"
     out = {
         "metric": METRIC,
@@ -639,6 +656,7 @@ def main():
             "launch_us": launch_ms * 1e3,
             "launch_us_with_event_pairs": head["stage_launch_us_with_event_pairs"],
         },
+        "stream_copy": stream_copy(),
         "fp64": head,
         "mixed": mixed,
         "rhs_only": {"value": dof / (ms_rhs * 1e-3), "unit": "DOF-updates/s", "ms_per_call": ms_rhs},
