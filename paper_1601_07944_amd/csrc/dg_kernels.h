@@ -1347,49 +1347,60 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
 // for d > 0, (Umin - Ubar) / d for d < 0, and 1 for d = 0; the smallest
 // factor, at most 1, scales modes 1 and 2.  Only those modes are written, so
 // reading the neighbours' means while other work-items limit is race-free.
-// Four work-items per element (one per variable) give a p = 1 mesh enough
-// wavefronts to fill the GPU.
-template <int P>
+// The neighbours' indices are read once per element, the own coefficients
+// and the neighbours' means of the four variables are all in flight
+// together, and the slopes are written with non-temporal stores.  BC: the
+// mesh has domain-boundary sides (periodic meshes skip the boundary kinds).
+template <int P, bool BC>
 __global__ __launch_bounds__(BLOCK) void k_limit_bj(int n, double* __restrict__ C, const int* __restrict__ snb,
-                                                    const int* __restrict__ sbc, const double* __restrict__ tab)
+                                                     const int* __restrict__ sbc, const double* __restrict__ tab)
 {
     using O = Ord<P>;
     constexpr int NP = O::NP, NE = O::NE;
     const double s2 = 1.4142135623730951;
-    // four work-items per element, one per conserved variable
-    const int t = blockIdx.x * BLOCK + threadIdx.x;
-    const int e = t >> 2, m = t & 3;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
     if (e >= n) return;
-    const int so = state_off(e, 4 * NP) + m * NP * LANES;
-    double c[NP];
+    const int so = state_off(e, 4 * NP);
+    int nbo[3];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) c[j] = C[so + j * LANES];
-    const double ub = s2 * c[0];
-    double umax = ub, umin = ub;
-    const int bcv = sbc[state_off(e, 1)];
+    for (int q = 0; q < 3; ++q) nbo[q] = state_off(snb[state_off(e, 3) + q * LANES], 4 * NP);
+    const int bcv = BC ? sbc[state_off(e, 1)] : 0;
+    double c[4][NP], un[3][4];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        // a domain-boundary side has no neighbour (its snb entry is the
-        // element itself, which leaves the bounds unchanged)
-        const double un = s2 * C[state_off(snb[state_off(e, 3) + q * LANES], 4 * NP) + m * NP * LANES];
-        if (((bcv >> (4 * q)) & 15) == 0) {
-            umax = fmax(umax, un);
-            umin = fmin(umin, un);
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) c[m][j] = C[so + (m * NP + j) * LANES];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) un[q][m] = s2 * C[nbo[q] + m * NP * LANES];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const double ub = s2 * c[m][0];
+        double umax = ub, umin = ub;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            // a domain-boundary side has no neighbour
+            if (!BC || ((bcv >> (4 * q)) & 15) == 0) {
+                umax = fmax(umax, un[q][m]);
+                umin = fmin(umin, un[q][m]);
+            }
         }
+        double a = 1.0;
+#pragma unroll
+        for (int qk = 0; qk < 3 * NE; ++qk) {
+            double u = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) u = fma(tab[O::PHS + qk * NP + j], c[m][j], u);
+            const double d = u - ub;
+            const double ak = d > 0.0 ? (umax - ub) / d : d < 0.0 ? (umin - ub) / d : 1.0;
+            a = fmin(a, ak);
+        }
+#pragma unroll
+        for (int j = 1; j < NP; ++j) __builtin_nontemporal_store(a * c[m][j], &C[so + (m * NP + j) * LANES]);
     }
-    double a = 1.0;
-#pragma unroll
-    for (int qk = 0; qk < 3 * NE; ++qk) {
-        double u = 0.0;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) u = fma(tab[O::PHS + qk * NP + j], c[j], u);
-        const double d = u - ub;
-        const double ak = d > 0.0 ? (umax - ub) / d : d < 0.0 ? (umin - ub) / d : 1.0;
-        a = fmin(a, ak);
-    }
-#pragma unroll
-    for (int j = 1; j < NP; ++j) C[so + j * LANES] = a * c[j];
 }
+
+
 
 // ---------------------------------------------------------------- adjoint
 // Cotangent of s = Fx(U).X + Fy(U).Y with respect to U (X, Y: cotangents of

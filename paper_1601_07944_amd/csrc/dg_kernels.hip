@@ -122,7 +122,10 @@ void launch_dt_final(const double* partial, int count, double cfl, double* dt_de
 void launch_limit(const MeshDev& m, double* C, hipStream_t s)
 {
     // the limiter is defined for p = 1 only (the caller checks)
-    k_limit_bj<1><<<grid_for(4 * m.n), BLOCK, 0, s>>>(m.n, C, m.side_nb, m.side_bc, m.tab);
+    if (m.has_bc)
+        k_limit_bj<1, true><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, C, m.side_nb, m.side_bc, m.tab);
+    else
+        k_limit_bj<1, false><<<grid_for(m.n), BLOCK, 0, s>>>(m.n, C, m.side_nb, m.side_bc, m.tab);
 }
 
 void launch_pack(const MeshDev& m, const double* Cu, double* C, hipStream_t s)
