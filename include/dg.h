@@ -375,8 +375,9 @@ int dg_limit(dg_mesh m, double* C_dev, void* stream);
  * DG_LANES4_MAX_ELEMENTS elements or for p >= 4, else 1; the adjoint
  * kernels of dg_rhs_vjp and dg_rk_step_vjp take 4 lanes from p = 3 on at
  * any size, where the one-lane adjoint holds too many values).  1 and 4
- * apply to both.  Both give the same result to rounding.  Returns DG_EINVAL
- * for any other value. */
+ * apply to both.  Both give the same result to rounding.  1 is refused
+ * (DG_EUNSUPPORTED) from p = 4 on, where an element's values exceed a
+ * lane's registers.  Returns DG_EINVAL for any value other than 0, 1, 4. */
 #define DG_LANES4_MAX_ELEMENTS 1048576
 int dg_set_lanes_per_element(dg_mesh m, int lanes);
 

@@ -930,6 +930,9 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes)
 {
     if (!m) return fail(DG_EINVAL, "null mesh");
     if (lanes != 0 && lanes != 1 && lanes != 4) return fail(DG_EINVAL, "lanes per element must be 0, 1 or 4");
+    if (lanes == 1 && m->dev.p >= 4)
+        return fail(DG_EUNSUPPORTED, "one lane per element holds more values than a lane has registers from p = 4 on "
+                                     "(p = %d): use 4 lanes (or 0, automatic)", m->dev.p);
     m->dev.lanes4 = lanes == 4 || (lanes == 0 && (m->dev.n <= DG_LANES4_MAX_ELEMENTS || m->dev.p >= 4));
     m->dev.vjp_lanes4 = lanes == 4 || (lanes == 0 && (m->dev.lanes4 || m->dev.p >= 3));
     return ok();

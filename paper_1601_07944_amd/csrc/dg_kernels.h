@@ -2087,12 +2087,15 @@ struct Launch {
     static void stage_m(const MeshDev& m, const T* tab, const double* C, const double* U0, double* out, double dt,
                         const double* dt_dev, hipStream_t s, const FusedDt& fz, const StageGen& gs)
     {
-        if (m.lanes4) {
+        // (one lane per element only up to p = 3: from p = 4 on its values
+        // exceed a lane's registers, and the library refuses it)
+        if (P >= 4 || m.lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
             k_stage4<P, MODE, T, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q,
                                                           m.side_g, tab, m.tab, m.gamma, dt, dt_dev, fz.pin,
                                                           fz.pin_count, fz.cfl, fz.dt_store, fz.dt_hist, fz.pout, gs,
                                                           m.side_bc, m.bc_state);
+        } else if constexpr (P >= 4) {
         } else if constexpr (sizeof(T) != sizeof(double)) {
             stage1_f32<P, MODE, BC>(m, tab, C, U0, out, dt, dt_dev, gs, s);
         } else {
@@ -2115,7 +2118,7 @@ struct Launch {
     static void stage_vjp_t(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X,
                             const double* Y, double* out, double dt, const double* dt_dev, hipStream_t s)
     {
-        if (m.vjp_lanes4) {
+        if (P >= 4 || m.vjp_lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
 #define DG_VJP4(MODE)                                                                                                  \
     k_stage_vjp4<P, MODE, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, Rb, X, Y, out, m.geo, m.side_nb, m.side_q, m.side_g, \
@@ -2129,6 +2132,7 @@ struct Launch {
 #undef DG_VJP4
             return;
         }
+        if constexpr (P <= 3) {
         const int nb = (m.npad + BLOCK - 1) / BLOCK;
         dim3 g((nb + 7) / 8 * 8);
 #define DG_VJP(MODE)                                                                                                 \
@@ -2141,6 +2145,7 @@ struct Launch {
         default: DG_VJP(3); break;
         }
 #undef DG_VJP
+        }
     }
     static void eval_points(const MeshDev& m, const double* C, double* u, hipStream_t s)
     {

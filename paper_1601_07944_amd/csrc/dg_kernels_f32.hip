@@ -1,4 +1,4 @@
-// One-lane FP32 stage kernels of orders p = 2..5 (templates in dg_kernels.h).
+// One-lane FP32 stage kernels of orders p = 2, 3 (templates in dg_kernels.h).
 // The build compiles this file alone with the max-memory-clause scheduler.
 #define DG_DEFINE_STAGE1_F32
 #include "dg_kernels.h"
@@ -6,6 +6,4 @@
 namespace dgk {
 DG_STAGE1_F32_ORDER(2)
 DG_STAGE1_F32_ORDER(3)
-DG_STAGE1_F32_ORDER(4)
-DG_STAGE1_F32_ORDER(5)
 }  // namespace dgk

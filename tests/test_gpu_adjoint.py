@@ -32,6 +32,8 @@ def rel_l2(a, b):
 
 
 def gpu_mesh(mesh, p, lanes=0):
+    if lanes == 1 and p >= 4:
+        pytest.skip("one lane per element is refused from p = 4 on (DG_EUNSUPPORTED)")
     from paper_1601_07944_amd import binding as B
 
     dm = B.DGMesh.from_mesh(mesh, p)

@@ -50,6 +50,8 @@ def box(kind, nx=14, ny=12, seed=4):
 
 
 def pair(mesh, p, lanes):
+    if lanes == 1 and p >= 4:
+        pytest.skip("one lane per element is refused from p = 4 on (DG_EUNSUPPORTED)")
     from paper_1601_07944_amd import binding as B
 
     orc = O.Oracle(mesh, p)

@@ -37,6 +37,9 @@ SURFACE = {"elementwise1": (ELEMENTWISE, 1), "elementwise4": (ELEMENTWISE, 4), "
 def gpu_mesh(mesh, p, surface=(ELEMENTWISE, 0)):
     from paper_1601_07944_amd import binding as B
 
+    if surface[1] == 1 and p >= 4:
+        pytest.skip("one lane per element is refused from p = 4 on (DG_EUNSUPPORTED)")
+
     dm = B.DGMesh.from_mesh(mesh, p)
     dm.set_surface_mode(surface[0])
     dm.set_lanes(surface[1])
@@ -400,3 +403,23 @@ def test_advance_equals_max_dt_plus_rk_step(lanes, prec):
         for _ in range(7):
             ref = orc.rk3_step(ref, orc.max_dt(ref, cfl)[0])
         check_close(dm.unpack(A).cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("p", [4, 5])
+def test_one_lane_refused_from_p4(p):
+    """From p = 4 on an element's coefficients and accumulators exceed one
+    lane's registers: dg_set_lanes_per_element(1) is refused, four lanes and
+    the automatic choice stay accepted, and the mesh keeps working."""
+    from paper_1601_07944_amd import binding as B
+
+    mesh = W.square_mesh(8, 1.0, 0.1, 3)
+    dm = B.DGMesh.from_mesh(mesh, p)
+    with pytest.raises(B.DGError) as ei:
+        dm.set_lanes(1)
+    assert ei.value.code == -4 and "p = 4" in str(ei.value)
+    dm.set_lanes(4)
+    dm.set_lanes(0)
+    C = dm.pack(to_dev(W.random_state(mesh.n_elem, dm.np, 5)))
+    R = dm.rhs(C)
+    assert bool(torch_mod().isfinite(R).all())
+    dm.close()
