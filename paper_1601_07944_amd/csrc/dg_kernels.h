@@ -910,10 +910,13 @@ __device__ __forceinline__ void rhs_quad(const Quad4<P, T>& z, const T (&c)[Ord<
     for (int j = 0; j < NP; ++j) acc[j] = T(0);
     acc0 = 0.0;
 
-    // the neighbours' coefficients of this lane's variable, two sides in
-    // flight: sides 0 and 1 before the volume integral, side 2 once side 0
-    // is done, so the gathers' latency overlaps arithmetic
-    constexpr int PF = 2;
+    // the neighbours' coefficients of this lane's variable, one side in
+    // flight: side 0's before the volume integral, each next side's once the
+    // previous side is done, so the gathers' latency overlaps arithmetic.
+    // (Two sides in flight hold N_p more values per lane: at p = 4 that
+    // costs a wavefront per SIMD and 16% of the time, at p = 5 3%; one side
+    // is no slower at p = 1..3.)
+    constexpr int PF = 1;
     const int sides = sside[state_off(e, 1)];
     const int* const nb = snb + state_off(e, 3);
     T cn[PF][NP];
@@ -1112,7 +1115,8 @@ __device__ __forceinline__ void rhs_quad_mfma(const Quad4<P, float>& z, const fl
     for (int g = 0; g < NG; ++g) av[g] = as[g] = zero;
     acc0 = 0.0;
 
-    constexpr int PF = 2;
+    // one neighbour side in flight, as in rhs_quad (two sides cost 12% at p=5)
+    constexpr int PF = 1;
     const int sides = sside[state_off(e, 1)];
     const int* const nb = snb + state_off(e, 3);
     float cn[PF][NP];
