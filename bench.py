@@ -117,15 +117,24 @@ def load_traffic(key: str):
         return None
 
 
-def auto_lanes(n_elem: int, p: int) -> int:
-    # the library's automatic choice (dg_set_lanes_per_element)
-    return 4 if (n_elem <= 1048576 or p >= 4) else 1
+def stage_kernel(dm, prec) -> int:
+    """The stage kernel the library's current choice runs for this precision:
+    1 or 4 lanes per element, or 16 (FP64 on the matrix cores)."""
+    from paper_1601_07944_amd import binding as B
+
+    fp64, lanes = dm.kernel_choice()
+    return fp64 if prec == B.DG_FP64 else lanes
 
 
-def stage_kernel_name(n_elem, p, prec="double"):
-    if auto_lanes(n_elem, p) == 4:
-        return f"k_stage4<{p}, 1..3, {prec}> (fused RHS: surface + volume + 1/det J + SSP-RK3 stage, 4 lanes per element)"
-    return f"k_stage<{p}, 1..3, {prec}> (fused RHS: surface + volume + 1/det J + SSP-RK3 stage, 1 lane per element)"
+def stage_kernel_name(dm, p, prec=0):
+    k = stage_kernel(dm, prec)
+    t = "double" if prec == 0 else "float"
+    what = "fused RHS: surface + volume + 1/det J + SSP-RK3 stage"
+    if k == 16:
+        return f"k_stage_mx<{p}, 1..3> ({what}, contractions on the matrix cores, 16 elements per wavefront)"
+    if k == 4:
+        return f"k_stage4<{p}, 1..3, {t}> ({what}, 4 lanes per element)"
+    return f"k_stage<{p}, 1..3, {t}> ({what}, 1 lane per element)"
 
 
 class Timer:
@@ -192,7 +201,7 @@ def advance_throughput(dm, C0, p, prec, steps, warmup, split_steps=10):
         "ms_per_step": ms,
         "ms_per_step_with_kernel_events": ms_split,
         "wall_s_timed_region": wall,
-        "lanes_per_element": auto_lanes(dm.n, p),
+        "kernel": stage_kernel_name(dm, p, prec),
         "precision": "fp64" if prec == B.DG_FP64 else "mixed",
         "kernel_ms_per_step": {k: v[0] / split_steps for k, v in kt.items() if v[1]},
     }
@@ -371,7 +380,7 @@ def orders_sweep(mesh, headline_p3, mixed_p3, steps, dev):
             del C0, dm
             torch.cuda.empty_cache()
         row["mixed_speedup"] = row["fp64"]["ms_per_step"] / row["mixed"]["ms_per_step"]
-        row["kernel"] = stage_kernel_name(mesh.n_elem, p)
+        row["kernel"] = row["fp64"]["kernel"]
         log(f"p={p}: fp64 {row['fp64']['value']:.3e} DOF/s ({row['fp64']['ms_per_step']:.3f} ms/step, "
             f"frac {row['fp64']['frac_hbm']:.3f}), mixed x{row['mixed_speedup']:.3f}")
         rows.append(row)
@@ -480,13 +489,15 @@ def cache_resident(steps, dev):
     res, C = advance_throughput(dm, C0, p, B.DG_FP64, steps, 5)
     res["workload"] = ("isentropic vortex, periodic [0,10]^2, 128x128x2 = 32,768 triangles jittered by 0.2h (seed 1), "
                        "p=3, FP64; the state (10.5 MB) stays in the last-level cache")
-    res["kernel"] = stage_kernel_name(dm.n, p)
     rmx, _ = advance_throughput(dm, C0, p, B.DG_MIXED, steps, 5)
     res["mixed"] = {"ms_per_step": rmx["ms_per_step"], "speedup_vs_fp64": res["ms_per_step"] / rmx["ms_per_step"]}
-    alt = 1 if auto_lanes(dm.n, p) == 4 else 4
-    dm.set_lanes(alt)
-    ra, _ = advance_throughput(dm, C0, p, B.DG_FP64, steps, 3)
-    res["lanes_alternative"] = {"lanes": alt, "ms_per_step": ra["ms_per_step"]}
+    # the other FP64 stage kernels on the same workload (an explicit lane
+    # count selects the vector-ALU kernels)
+    res["alternatives"] = {}
+    for lanes in (4, 1):
+        dm.set_lanes(lanes)
+        ra, _ = advance_throughput(dm, C0, p, B.DG_FP64, steps, 3)
+        res["alternatives"][ra["kernel"]] = {"ms_per_step": ra["ms_per_step"], "stage_launch_us": ra.get("stage_launch_us")}
     dm.set_lanes(0)
     for name, mode in (("surface_edgewise", dm.SURFACE_EDGEWISE), ("surface_coloured", dm.SURFACE_COLOURED)):
         dm.set_surface_mode(mode)
@@ -629,7 +640,7 @@ def main():
     launch_ms = head["stage_launch_us"] * 1e-3
     ach = head["stage_hbm_GBs_algorithmic"]
     log("stream copy ...")
-    tkey = f"stage_p3_delaunay4m_{'lanes4' if auto_lanes(dm.n, p) == 4 else 'lanes1'}"
+    tkey = f"stage_p3_delaunay4m_{ {1: 'lanes1', 4: 'lanes4', 16: 'mx'}[stage_kernel(dm, B.DG_FP64)] }"
     out = {
         "metric": METRIC,
         "value": head["value"],
@@ -645,7 +656,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": TARGET_WORKLOAD, "n_elem": dm.n, "p": p, "dof": dof},
         "roofline": {
-            "kernel": stage_kernel_name(dm.n, p),
+            "kernel": stage_kernel_name(dm, p),
             "bound": "hbm",
             "achieved": ach,
             "peak": HBM_PEAK_GBS,

@@ -51,6 +51,7 @@ EXPORTS = [
     "dg_eval_points",
     "dg_quad_weights",
     "dg_set_lanes_per_element",
+    "dg_set_matrix_cores",
     "dg_set_surface_mode",
     "dg_set_stream_concurrency",
     "dg_set_boundary_state",
@@ -84,6 +85,8 @@ class dg_info(ctypes.Structure):
         ("ws_step", ctypes.c_int64),
         ("ws_vjp", ctypes.c_int64),
         ("n_colours", ctypes.c_int64),
+        ("stage_fp64", ctypes.c_int),
+        ("lanes", ctypes.c_int),
     ]
 
 
@@ -125,6 +128,7 @@ def load(path: str = LIB_PATH):
     lib.dg_eval_points.argtypes = [_vp, _vp, _vp, _vp]
     lib.dg_quad_weights.argtypes = [_vp, _vp, _vp]
     lib.dg_set_lanes_per_element.argtypes = [_vp, i32]
+    lib.dg_set_matrix_cores.argtypes = [_vp, i32]
     lib.dg_set_surface_mode.argtypes = [_vp, i32]
     lib.dg_set_stream_concurrency.argtypes = [_vp, i32]
     lib.dg_set_boundary_state.argtypes = [_vp, _dp]
@@ -346,6 +350,18 @@ class DGMesh:
     def set_lanes(self, lanes: int):
         """Work-items per element in the element-wise kernels: 0 (auto), 1 or 4."""
         _check(self._lib.dg_set_lanes_per_element(self._h, int(lanes)))
+
+    def kernel_choice(self):
+        """(FP64 stage kernel: 1 or 4 lanes per element, or 16 = matrix cores;
+        lanes per element of the mixed-precision stages) of the current choice."""
+        info = dg_info()
+        _check(self._lib.dg_mesh_info(self._h, ctypes.byref(info)))
+        return info.stage_fp64, info.lanes
+
+    def set_matrix_cores(self, on):
+        """FP64 stages with their contractions on the matrix cores: True, False,
+        or None (automatic, the default)."""
+        _check(self._lib.dg_set_matrix_cores(self._h, -1 if on is None else (1 if on else 0)))
 
     def set_surface_mode(self, mode: int):
         _check(self._lib.dg_set_surface_mode(self._h, int(mode)))

@@ -29,6 +29,9 @@ struct dg_mesh_s {
     int surface = DG_SURFACE_ELEMENTWISE;
     int limiter = DG_LIMITER_NONE;
     int integrator = DG_RK_SSP3;
+    // kernel choice as requested: lanes per element (0 automatic, 1, 4) and
+    // matrix cores (-1 automatic, 0 off, 1 on); apply_kernel_choice sets dev
+    int lanes_req = 0, mx_req = -1;
     size_t off_acc = 0;  // RK4 accumulator state in the step workspace
     size_t off_V = 0;    // volume integral of the two-stream edge-wise path
     // edge-wise path: volume integral on a second stream beside the traces
@@ -46,6 +49,26 @@ struct dg_mesh_s {
 };
 
 namespace {
+
+// The automatic kernel choice (measured on MI355X, FP64 stages; mixed
+// precision and the adjoint follow the lane choice only):
+//   lanes: four per element up to DG_LANES4_MAX_ELEMENTS elements or from
+//     p = 4 on, else one; the adjoint four from p = 3 on;
+//   matrix cores: at p = 4 at every size, at p = 3 and 5 up to
+//     DG_LANES4_MAX_ELEMENTS elements (beyond that the one-lane kernel at
+//     p = 3 and the four-lane kernel at p = 5 are faster), never at p <= 2
+//     (the 16 x 4 products would be mostly padding).
+// An explicit lane count keeps the vector-ALU kernels unless the matrix
+// cores are switched on explicitly.
+void apply_kernel_choice(dg_mesh m)
+{
+    dgk::MeshDev& d = m->dev;
+    const bool small = d.n <= DG_LANES4_MAX_ELEMENTS;
+    d.lanes4 = m->lanes_req == 4 || (m->lanes_req == 0 && (small || d.p >= 4));
+    d.vjp_lanes4 = m->lanes_req == 4 || (m->lanes_req == 0 && (d.lanes4 || d.p >= 3));
+    const bool mx_auto = m->lanes_req == 0 && (d.p == 4 || ((d.p == 3 || d.p == 5) && small));
+    d.mx = m->mx_req == 1 || (m->mx_req == -1 && mx_auto);
+}
 
 thread_local std::string g_err;
 
@@ -386,11 +409,13 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         return DG_OK;
     };
     std::vector<float> tab32(tab.begin(), tab.end());
-    void *d_tab32;
+    std::vector<double> tabmx = dgh::build_mx_tables(p, tab, lay);
+    void *d_tab32, *d_tabmx;
     void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg, *d_snb, *d_sside, *d_sg, *d_sbc, *d_bcs;
     void *d_ecol, *d_egc;
     const double bc_state0[4] = {1.0, 0.0, 0.0, 1.0 / (gamma - 1.0)};  // until dg_set_boundary_state: at rest, p = 1
-    if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(tab32.data(), tab32.size() * 4, &d_tab32)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
+    if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(tab32.data(), tab32.size() * 4, &d_tab32)) ||
+        (rc = upload(tabmx.data(), tabmx.size() * 8, &d_tabmx)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
         (rc = upload(vtx.data(), vtx.size() * 8, &d_vtx)) || (rc = upload(perm.data(), perm.size() * 4, &d_perm)) ||
         (rc = upload(el.data(), el.size() * 4, &d_el)) || (rc = upload(er.data(), er.size() * 4, &d_er)) ||
         (rc = upload(sd.data(), sd.size() * 4, &d_sd)) || (rc = upload(eg.data(), eg.size() * 8, &d_eg)) ||
@@ -415,10 +440,9 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.edge_gc = (const double*)d_egc;
     for (int c = 0; c <= ncolour; ++c) d.colour_off[c] = colour_off[c];
     d.gamma = gamma;
-    d.lanes4 = N <= DG_LANES4_MAX_ELEMENTS || p >= 4;
-    d.vjp_lanes4 = d.lanes4 || p >= 3;
     d.tab = (const double*)d_tab;
     d.tab32 = (const float*)d_tab32;
+    d.tabmx = (const double*)d_tabmx;
     d.geo = (const double*)d_geo;
     d.vtx = (const double*)d_vtx;
     d.perm = (const int*)d_perm;
@@ -433,6 +457,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.bc_state = (double*)d_bcs;
     d.has_bc = has_bc;
     m->lay = lay;
+    apply_kernel_choice(m);
 
     const size_t state = align256((size_t)npad * 4 * np * 8);
     const size_t trace = align256((size_t)npad * 3 * ne * 4 * 8);
@@ -494,6 +519,8 @@ int dg_mesh_info(dg_mesh m, dg_info* out)
     out->ws_rhs = m->ws_rhs;
     out->ws_step = m->ws_step;
     out->ws_vjp = m->ws_vjp;
+    out->lanes = m->dev.lanes4 ? 4 : 1;
+    out->stage_fp64 = m->dev.mx ? 16 : out->lanes;
     return ok();
 }
 
@@ -821,7 +848,10 @@ int dg_advance(dg_mesh m, double* C, int64_t nsteps, double cfl, double* dt_dev,
     char* w = (char*)ws;
     double* part = (double*)(w + m->off_part);
     double* part4 = (double*)(w + m->off_part4);
-    if (m->surface != DG_SURFACE_ELEMENTWISE || !d.lanes4 || m->integrator != DG_RK_SSP3) {
+    // the per-64-element minima of the fused step length come from the
+    // four-lane and matrix-core stage kernels
+    const bool fused_dt = d.lanes4 || (d.mx && prec == DG_FP64);
+    if (m->surface != DG_SURFACE_ELEMENTWISE || !fused_dt || m->integrator != DG_RK_SSP3) {
         // separate reduction each step
         for (int64_t k = 0; k < nsteps; ++k) {
             timed(m, DG_KERNEL_DT, s, [&] {
@@ -933,8 +963,18 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes)
     if (lanes == 1 && m->dev.p >= 4)
         return fail(DG_EUNSUPPORTED, "one lane per element holds more values than a lane has registers from p = 4 on "
                                      "(p = %d): use 4 lanes (or 0, automatic)", m->dev.p);
-    m->dev.lanes4 = lanes == 4 || (lanes == 0 && (m->dev.n <= DG_LANES4_MAX_ELEMENTS || m->dev.p >= 4));
-    m->dev.vjp_lanes4 = lanes == 4 || (lanes == 0 && (m->dev.lanes4 || m->dev.p >= 3));
+    m->lanes_req = lanes;
+    apply_kernel_choice(m);
+    return ok();
+}
+
+int dg_set_matrix_cores(dg_mesh m, int on)
+{
+    if (!m) return fail(DG_EINVAL, "null mesh");
+    if (on != 0 && on != 1 && on != -1)
+        return fail(DG_EINVAL, "matrix cores: -1 (automatic), 0 (off) or 1 (on), not %d", on);
+    m->mx_req = on;
+    apply_kernel_choice(m);
     return ok();
 }
 

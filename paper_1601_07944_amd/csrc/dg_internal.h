@@ -20,6 +20,8 @@ void volume_rule(int p, std::vector<double>& r, std::vector<double>& s, std::vec
 void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
 void side_point(int q, double xi, double* r, double* s);
 std::vector<double> build_tables(int p, TableLayout* lay);
+// the table operands of the matrix-core stage kernel from build_tables' output
+std::vector<double> build_mx_tables(int p, const std::vector<double>& tab, const TableLayout& lay);
 
 }  // namespace dgh
 
@@ -33,6 +35,45 @@ namespace dgk {
 constexpr int LANES = 16;
 constexpr int WAVE = 64;
 
+// Table operands of the FP64 matrix-core stage kernel (k_stage_mx): blocks
+// of 64 doubles, one per lane, in the operand order of the 16 x 16 x 4 FP64
+// matrix product (lane 16 k + i holds row i, column k of the 16 x 4 table
+// operand; register r of lane 16 g + j of the product is row 4 r + g).
+// Lane 16 g + j of that kernel holds modes 4 s + g (s < KP) of element j of
+// a 16-element block; point and side-point rows come in tiles of 16, and so
+// do mode rows (row i of mode tile tm is mode 16 tm + i).
+//   PHI [t][s]      phi_{4s+k} at volume point 16t+i (last point repeated)
+//   DR, DS [tm][t][s']  w dphi/dr, w dphi/ds of mode 16tm+i at volume point
+//                   16t+4s'+k (zero past the last point)
+//   PE [ts][s]      phi_{4s+k} at side point 16ts+i (side-major: point k of
+//                   side q is q(p+1)+k; last side point repeated)
+//   LE [tm][ts][s'] Gauss weight times phi of mode 16tm+i at side point
+//                   16ts+4s'+k (zero past the last side point)
+// Entries of modes >= N_p are zero.
+struct MxLayout {
+    int np, nq, ne, ns, kp, tq, ts, tm;
+    int phi, dr, ds, pe, le, blocks;
+};
+constexpr MxLayout mx_layout(int p)
+{
+    MxLayout x{};
+    x.np = (p + 1) * (p + 2) / 2;
+    x.nq = p == 1 ? 3 : p == 2 ? 6 : p == 3 ? 12 : p == 4 ? 16 : 25;
+    x.ne = p + 1;
+    x.ns = 3 * x.ne;
+    x.kp = (x.np + 3) / 4;
+    x.tq = (x.nq + 15) / 16;
+    x.ts = (x.ns + 15) / 16;
+    x.tm = (x.kp + 3) / 4;
+    x.phi = 0;
+    x.dr = x.phi + x.tq * x.kp;
+    x.ds = x.dr + x.tm * x.tq * 4;
+    x.pe = x.ds + x.tm * x.tq * 4;
+    x.le = x.pe + x.ts * x.kp;
+    x.blocks = x.le + x.tm * x.ts * 4;
+    return x;
+}
+
 // Device view of a mesh, passed by value to the launchers.
 struct MeshDev {
     int p = 0, np = 0, nq = 0, ne = 0;
@@ -41,6 +82,7 @@ struct MeshDev {
     int nedge = 0;
     bool lanes4 = false;  // fused kernels: 4 lanes per element instead of 1
     bool vjp_lanes4 = true;  // adjoint kernels: 4 lanes per element instead of 1
+    bool mx = false;         // FP64 stages on the matrix cores (k_stage_mx) instead of k_stage4
     // domain boundaries: per element 4 bits per side (0 interior, 1 wall,
     // 2 outflow, 3 prescribed state), and the prescribed state (4 doubles)
     const int* side_bc = nullptr;
@@ -49,6 +91,7 @@ struct MeshDev {
     double gamma = 1.4;
     const double* tab = nullptr;      // reference tables (TableLayout)
     const float* tab32 = nullptr;     // the same tables rounded to FP32 (mixed precision)
+    const double* tabmx = nullptr;    // table operands of k_stage_mx (MxLayout)
     const double* geo = nullptr;      // [blk][6][LANES]: adj00 adj01 adj10 adj11 1/detJ r_in
     const double* vtx = nullptr;      // [npad][6] vertices (internal order), setup only
     const int* perm = nullptr;        // internal -> user element id

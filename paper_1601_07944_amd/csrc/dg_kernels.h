@@ -1340,6 +1340,261 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     }
 }
 
+// ---------------------------------------------------------------- FP64 stage on the matrix cores
+// The fused stage of k_stage4 in FP64 with every contraction of eq. (2ddg0)
+// on v_mfma_f64_16x16x4f64: one wavefront per block of 16 elements, the
+// elements are the 16 columns of each product.  Operand layout of that
+// instruction: the 16 x 4 table operand A has row i, column k in lane 16k+i;
+// the 4 x 16 operand B has row k, column j in lane 16k+j; register r of the
+// 16 x 16 result in lane 16g+j is row 4r+g, column j.
+// Lane 16g+j holds modes 4s+g (s < KP) of the four variables of element j:
+// the B operands of every contraction over modes (k-step s).
+//   evaluation at 16 points (volume, eq. (volume), or the three sides' Gauss
+//     points, eq. (surface)): register r of lane group g is point 4r+g of
+//     the tile, all four variables at four points per lane, which is what
+//     the fluxes need: no exchange between lanes;
+//   lift back to modes: the lane's fluxes at its points are the B operands,
+//     k-step s' pairing lane group g with point 4s'+g (the table operand is
+//     ordered to match), and register r of lane group g of mode tile tm is
+//     mode 16tm+4r+g = 4(4tm+r)+g: the lane's own modes, so the stage update
+//     needs no exchange either.
+// The neighbour's trace across side q is the neighbour's side q' at the
+// reversed point; q' differs between the columns, so the neighbour's traces
+// on all three sides are evaluated (one product per side) and each lane
+// picks its points through LDS.  Padded points repeat a real one (finite
+// fluxes) and carry zero weights; padded modes have zero table entries.
+#ifndef DG_MX_NVH
+#define DG_MX_NVH 2
+#endif
+typedef double dx4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ dx4 mfma64(double a, double b, dx4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// at p = 4 the kernel without domain boundaries fits three wavefronts per
+// SIMD without spilling (168 registers) when asked to (the boundary
+// variants and p = 5 would spill; p <= 3 fits three by itself)
+template <int P, bool BC>
+constexpr int mx_waves = P == 4 && !BC ? 3 : 1;
+template <int P, int MODE, bool BC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<P, BC>))) void k_stage_mx(int n, int npad, const double* __restrict__ C,
+                                                    const double* __restrict__ U0, double* __restrict__ out,
+                                                    const double* __restrict__ geo, const int* __restrict__ snb,
+                                                    const int* __restrict__ sside, const double* __restrict__ sgeo,
+                                                    const double* __restrict__ tmx, double gamma, double dt,
+                                                    const double* __restrict__ dt_dev, const double* __restrict__ pin,
+                                                    int pin_count, double cfl, double* __restrict__ dt_store,
+                                                    double* __restrict__ dt_hist, double* __restrict__ pout,
+                                                    StageGen gs, const int* __restrict__ sbc,
+                                                    const double* __restrict__ bcs)
+{
+    constexpr MxLayout X = mx_layout(P);
+    constexpr int NP = X.np, NE = X.ne, NS = X.ns, KP = X.kp, TQ = X.tq, TS = X.ts, TM = X.tm;
+    constexpr int NW = BLOCK / WAVE;
+    constexpr int NVH = DG_MX_NVH;
+    __shared__ double xs[NW][3][4][NE][LANES];  // neighbour traces facing each side, per wavefront
+    __shared__ double red[NW];
+
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    double hfused = 0.0;
+    if constexpr (MODE == 1) {
+        if (pin) hfused = dt_from_partials(pin, pin_count, cfl, red);
+    }
+
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE, j = lane % 16, g = lane / 16;
+    const int blk = lb * NW + w;  // 16-element block of this wavefront
+    if (lb * NW * LANES >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
+    const int e = blk * LANES + j;
+    const bool real = e < n;
+    const double* gp = geo + state_off(e, 6);
+    const double a00 = gp[0], a01 = gp[LANES], a10 = gp[2 * LANES], a11 = gp[3 * LANES], idet = gp[4 * LANES];
+    const double gm1 = gamma - 1.0;
+    const int base = blk * 4 * NP * LANES + j;
+    const double* tl = tmx + lane;
+    auto A = [&](int b) { return tl[b * WAVE]; };
+
+    // own coefficients: c[v][s] = mode 4s+g of variable v (a padded mode
+    // loads the last mode; its table entries are zero)
+    double c[4][KP];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int s = 0; s < KP; ++s) c[v][s] = C[base + (v * NP + min(4 * s + g, NP - 1)) * LANES];
+
+    dx4 acc[4][TM];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int t = 0; t < TM; ++t) acc[v][t] = dx4{0.0, 0.0, 0.0, 0.0};
+
+    // volume integral, eq. (volume)
+#pragma unroll
+    for (int tq = 0; tq < TQ; ++tq) {
+        dx4 u[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) u[v] = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KP; ++s) {
+            const double a = A(X.phi + tq * KP + s);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) u[v] = mfma64(a, c[v][s], u[v]);
+        }
+        // the flux at the lane's point r is k-step r of the lift
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double U[4] = {u[0][r], u[1][r], u[2][r], u[3][r]};
+            double Fx[4], Fy[4];
+            euler_flux<double>(gm1, U, Fx, Fy);
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) {
+                const double ar = A(X.dr + (tm * TQ + tq) * 4 + r), as = A(X.ds + (tm * TQ + tq) * 4 + r);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    acc[v][tm] = mfma64(ar, a00 * Fx[v] + a01 * Fy[v], acc[v][tm]);
+                    acc[v][tm] = mfma64(as, a10 * Fx[v] + a11 * Fy[v], acc[v][tm]);
+                }
+            }
+        }
+    }
+
+    // surface integral, eq. (surface): the neighbours' traces first, side
+    // by side; each column keeps, in LDS, the p+1 points of its neighbour's
+    // side that face it, in its own order (reversed), so no lane holds
+    // neighbour values across the sides (register r of tile ts of lane
+    // group g is side point 16ts+4r+g, side-major)
+    const int sides = sside[state_off(e, 1)];
+    const int* const nb = snb + state_off(e, 3);
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        const int nbase = state_off(nb[q * LANES], 4 * NP);
+        const int qn = (sides >> (2 * q)) & 3;
+        // two variables at a time (half the registers of all four)
+#pragma unroll
+        for (int v0 = 0; v0 < 4; v0 += NVH) {
+            double cn[NVH][KP];
+#pragma unroll
+            for (int v = 0; v < NVH; ++v)
+#pragma unroll
+                for (int s = 0; s < KP; ++s)
+                    cn[v][s] = C[nbase + ((v0 + v) * NP + min(4 * s + g, NP - 1)) * LANES];
+#pragma unroll
+            for (int ts = 0; ts < TS; ++ts) {
+                dx4 tn[NVH];
+#pragma unroll
+                for (int v = 0; v < NVH; ++v) tn[v] = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KP; ++s) {
+                    const double a = A(X.pe + ts * KP + s);
+#pragma unroll
+                    for (int v = 0; v < NVH; ++v) tn[v] = mfma64(a, cn[v][s], tn[v]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * ts + 4 * r + g - qn * NE;  // point of the neighbour's side qn
+                    if (k >= 0 && k < NE) {
+#pragma unroll
+                        for (int v = 0; v < NVH; ++v) xs[w][q][v0 + v][NE - 1 - k][j] = tn[v][r];
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+
+    // own traces, the numerical flux eq. (llf) at each side point, scaled
+    // by minus the half side length (the Gauss weights are in the table),
+    // and the lift
+    const int bcv = BC ? sbc[state_off(e, 1)] : 0;
+    double G[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) G[v] = BC ? bcs[v] : 0.0;
+#pragma unroll
+    for (int ts = 0; ts < TS; ++ts) {
+        dx4 ul[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ul[v] = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KP; ++s) {
+            const double a = A(X.pe + ts * KP + s);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ul[v] = mfma64(a, c[v][s], ul[v]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int sp = 16 * ts + 4 * r + g;
+            const int q = min(sp / NE, 2);
+            const bool pad = sp >= NS;
+            const int go = state_off(e, 9) + 3 * q * LANES;
+            const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
+            const int k = min(sp - q * NE, NE - 1);
+            double UL[4], UR[4], F[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                UL[v] = ul[v][r];
+                UR[v] = pad ? UL[v] : xs[w][q][v][k][j];
+            }
+            if constexpr (BC) ghost_state<double>((bcv >> (4 * q)) & 15, UL, nx, ny, G, UR);
+            llf<double>(gamma, gm1, UL, UR, nx, ny, F);
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) {
+                const double a = A(X.le + (tm * TS + ts) * 4 + r);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v][tm] = mfma64(a, -hl * F[v], acc[v][tm]);
+            }
+        }
+    }
+
+    // 1/det J (orthonormal basis) and the stage update
+    double h = MODE == 0 ? 0.0 : (dt_dev ? dt_dev[0] : dt);
+    if constexpr (MODE == 1) {
+        if (pin) {
+            h = hfused;
+            if (lb == 0 && threadIdx.x == 0) {
+                dt_store[0] = h;
+                if (dt_hist) dt_hist[0] = h;
+            }
+        }
+    }
+    double mean[4] = {0.0, 0.0, 0.0, 0.0};  // new mode 0 (lane group 0)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int s = 0; s < KP; ++s) {
+            const int jm = 4 * s + g;
+            if (jm < NP) {
+                const int x = base + (v * NP + jm) * LANES;
+                const double L = idet * acc[v][s / 4][s % 4];
+                double val;
+                if (!real) {
+                    val = 0.0;
+                } else if constexpr (MODE == 0) {
+                    val = L;
+                } else {
+                    const double cs = c[v][s];
+                    if constexpr (MODE == 1)
+                        val = cs + h * L;
+                    else if constexpr (MODE == 2)
+                        val = 0.75 * __builtin_nontemporal_load(&U0[x]) + 0.25 * (cs + h * L);
+                    else if constexpr (MODE == 3)
+                        val = (1.0 / 3.0) * __builtin_nontemporal_load(&out[x]) + (2.0 / 3.0) * (cs + h * L);
+                    else
+                        val = stage_general(gs, cs, h, L, x, out);
+                }
+                __builtin_nontemporal_store(val, &out[x]);
+                if (s == 0) mean[v] = val;
+            }
+        }
+    if constexpr (MODE == 3) {
+        if (pout) {
+            double val = INFINITY;
+            if (real && g == 0) val = dt_local(gamma, gp[5 * LANES], mean[0], mean[1], mean[2], mean[3]);
+            const double mn = block_min(val, red);
+            if (threadIdx.x == 0) pout[lb] = mn;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- limiter
 // Barth-Jespersen slope limiter for p = 1 (Section "Limiting Kernel", eqs.
 // (limit), (limitmax), (limitmin)), in place, one work-item per element and
@@ -2093,6 +2348,16 @@ struct Launch {
     {
         // (one lane per element only up to p = 3: from p = 4 on its values
         // exceed a lane's registers, and the library refuses it)
+        if constexpr (sizeof(T) == sizeof(double)) {
+            if (m.mx) {
+                dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
+                k_stage_mx<P, MODE, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q,
+                                                             m.side_g, m.tabmx, m.gamma, dt, dt_dev, fz.pin,
+                                                             fz.pin_count, fz.cfl, fz.dt_store, fz.dt_hist, fz.pout,
+                                                             gs, m.side_bc, m.bc_state);
+                return;
+            }
+        }
         if (P >= 4 || m.lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
             k_stage4<P, MODE, T, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q,

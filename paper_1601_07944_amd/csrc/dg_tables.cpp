@@ -24,6 +24,7 @@
 // Integration Kernel") by Newton on the Legendre polynomial, symmetrised so
 // that node p-k is exactly -node k with an identical weight: the two
 // elements sharing an edge then evaluate bitwise the same physical points.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -331,6 +332,42 @@ std::vector<double> build_tables(int p, TableLayout* lay)
     for (int k = 0; k < ne; ++k) t[L.gw + k] = gw[k];
     if (lay) *lay = L;
     return t;
+}
+
+std::vector<double> build_mx_tables(int p, const std::vector<double>& t, const TableLayout& L)
+{
+    const dgk::MxLayout x = dgk::mx_layout(p);
+    std::vector<double> o((size_t)x.blocks * 64, 0.0);
+    auto put = [&](int blk, int lane, double v) { o[(size_t)blk * 64 + lane] = v; };
+    for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane % 16, k = lane / 16;
+        for (int tq = 0; tq < x.tq; ++tq)
+            for (int s = 0; s < x.kp; ++s) {
+                const int pt = std::min(16 * tq + i, x.nq - 1), j = 4 * s + k;
+                put(x.phi + tq * x.kp + s, lane, j < x.np ? t[L.phi + pt * x.np + j] : 0.0);
+            }
+        for (int tm = 0; tm < x.tm; ++tm)
+            for (int tq = 0; tq < x.tq; ++tq)
+                for (int s = 0; s < 4; ++s) {
+                    const int j = 16 * tm + i, pt = 16 * tq + 4 * s + k, b = (tm * x.tq + tq) * 4 + s;
+                    const bool in = j < x.np && pt < x.nq;
+                    put(x.dr + b, lane, in ? t[L.drw + pt * x.np + j] : 0.0);
+                    put(x.ds + b, lane, in ? t[L.dsw + pt * x.np + j] : 0.0);
+                }
+        for (int ts = 0; ts < x.ts; ++ts)
+            for (int s = 0; s < x.kp; ++s) {
+                const int sp = std::min(16 * ts + i, x.ns - 1), j = 4 * s + k;
+                put(x.pe + ts * x.kp + s, lane, j < x.np ? t[L.phs + sp * x.np + j] : 0.0);
+            }
+        for (int tm = 0; tm < x.tm; ++tm)
+            for (int ts = 0; ts < x.ts; ++ts)
+                for (int s = 0; s < 4; ++s) {
+                    const int j = 16 * tm + i, sp = 16 * ts + 4 * s + k;
+                    const bool in = j < x.np && sp < x.ns;
+                    put(x.le + (tm * x.ts + ts) * 4 + s, lane, in ? t[L.gw + sp % x.ne] * t[L.phs + sp * x.np + j] : 0.0);
+                }
+    }
+    return o;
 }
 
 }  // namespace dgh
