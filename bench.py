@@ -122,8 +122,8 @@ def stage_kernel(dm, prec) -> int:
     1 or 4 lanes per element, or 16 (FP64 on the matrix cores)."""
     from paper_1601_07944_amd import binding as B
 
-    fp64, lanes = dm.kernel_choice()
-    return fp64 if prec == B.DG_FP64 else lanes
+    fp64, mixed = dm.kernel_choice()
+    return fp64 if prec == B.DG_FP64 else mixed
 
 
 def stage_kernel_name(dm, p, prec=0):
@@ -131,7 +131,7 @@ def stage_kernel_name(dm, p, prec=0):
     t = "double" if prec == 0 else "float"
     what = "fused RHS: surface + volume + 1/det J + SSP-RK3 stage"
     if k == 16:
-        return f"k_stage_mx<{p}, 1..3> ({what}, contractions on the matrix cores, 16 elements per wavefront)"
+        return f"k_stage_mx<{p}, 1..3, {t}> ({what}, 16 x 16 x 4 matrix products, 16 elements per wavefront)"
     if k == 4:
         return f"k_stage4<{p}, 1..3, {t}> ({what}, 4 lanes per element)"
     return f"k_stage<{p}, 1..3, {t}> ({what}, 1 lane per element)"

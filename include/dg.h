@@ -102,9 +102,9 @@ typedef struct {
     int64_t ws_step;    /* workspace bytes for dg_rk_step and dg_rk_step_stages */
     int64_t ws_vjp;     /* workspace bytes for dg_rk_step_vjp */
     int64_t n_colours;  /* colours of the edge colouring (DG_SURFACE_COLOURED) */
-    int stage_fp64;     /* FP64 element-wise stage kernel of the current choice: 1 or 4 lanes per
-                           element (vector ALU) or 16 (matrix cores, 16 elements per wavefront) */
-    int lanes;          /* lanes per element of the mixed-precision stages (1 or 4) */
+    int stage_fp64;     /* element-wise stage kernel of the current choice in FP64: 1 or 4 lanes
+                           per element or 16 (16 x 16 x 4 matrix products, 16 elements per wavefront) */
+    int stage_mixed;    /* the same for DG_MIXED */
 } dg_info;
 
 /* Checks a mesh without touching the GPU (no HIP call).  Arguments as for
@@ -386,17 +386,18 @@ int dg_limit(dg_mesh m, double* C_dev, void* stream);
 #define DG_LANES4_MAX_ELEMENTS 1048576
 int dg_set_lanes_per_element(dg_mesh m, int lanes);
 
-/* FP64 right-hand side and RK stages with their contractions (eq. (2ddg0):
+/* Right-hand side and RK stages with their contractions (eq. (2ddg0):
  * evaluation of the modes at the volume and side points, the volume and
- * surface lifts) on the matrix cores: 16 x 16 x 4 FP64 products with the 16
- * elements of a block as the columns, one wavefront per block, four lanes per
- * element.  on: 1 uses that kernel for every FP64 stage, whatever the lane
- * count; 0 the vector-ALU kernels chosen by dg_set_lanes_per_element; -1
- * (the default) automatic: the matrix cores at p = 4 at every size and at
- * p = 3 and 5 up to DG_LANES4_MAX_ELEMENTS elements, as long as the lane
- * count is automatic too (an explicit 1 or 4 keeps the vector-ALU kernels).
- * Mixed precision and the adjoint are unaffected.  Same result to rounding.
- * Returns DG_EINVAL for other values of on. */
+ * surface lifts) as 16 x 16 x 4 matrix products on the matrix cores (FP64
+ * products in FP64, FP32 products in DG_MIXED), the 16 elements of a block
+ * as the columns, one wavefront per block, four lanes per element.  on: 1
+ * uses that kernel for every stage, whatever the lane count; 0 the
+ * vector-ALU kernels chosen by dg_set_lanes_per_element; -1 (the default)
+ * automatic: the matrix cores at p = 4 at every size and at p = 3 and 5 up
+ * to DG_LANES4_MAX_ELEMENTS elements, as long as the lane count is automatic
+ * too (an explicit 1 or 4 keeps the vector-ALU kernels).  The adjoint is
+ * unaffected.  Same result to rounding.  Returns DG_EINVAL for other values
+ * of on. */
 int dg_set_matrix_cores(dg_mesh m, int on);
 
 /* Per-kernel timing (the paper's kernel runtime distribution, measured with

@@ -86,7 +86,7 @@ class dg_info(ctypes.Structure):
         ("ws_vjp", ctypes.c_int64),
         ("n_colours", ctypes.c_int64),
         ("stage_fp64", ctypes.c_int),
-        ("lanes", ctypes.c_int),
+        ("stage_mixed", ctypes.c_int),
     ]
 
 
@@ -352,11 +352,11 @@ class DGMesh:
         _check(self._lib.dg_set_lanes_per_element(self._h, int(lanes)))
 
     def kernel_choice(self):
-        """(FP64 stage kernel: 1 or 4 lanes per element, or 16 = matrix cores;
-        lanes per element of the mixed-precision stages) of the current choice."""
+        """Stage kernels of the current choice, (FP64, mixed precision): 1 or 4
+        lanes per element, or 16 (16 x 16 x 4 matrix products)."""
         info = dg_info()
         _check(self._lib.dg_mesh_info(self._h, ctypes.byref(info)))
-        return info.stage_fp64, info.lanes
+        return info.stage_fp64, info.stage_mixed
 
     def set_matrix_cores(self, on):
         """FP64 stages with their contractions on the matrix cores: True, False,

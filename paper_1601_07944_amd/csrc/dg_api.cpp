@@ -68,6 +68,7 @@ void apply_kernel_choice(dg_mesh m)
     d.vjp_lanes4 = m->lanes_req == 4 || (m->lanes_req == 0 && (d.lanes4 || d.p >= 3));
     const bool mx_auto = m->lanes_req == 0 && (d.p == 4 || ((d.p == 3 || d.p == 5) && small));
     d.mx = m->mx_req == 1 || (m->mx_req == -1 && mx_auto);
+    d.mx32 = d.mx;
 }
 
 thread_local std::string g_err;
@@ -409,13 +410,16 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
         return DG_OK;
     };
     std::vector<float> tab32(tab.begin(), tab.end());
-    std::vector<double> tabmx = dgh::build_mx_tables(p, tab, lay);
-    void *d_tab32, *d_tabmx;
+    std::vector<double> tabmx = dgh::build_mx_tables(p, tab, lay, true);
+    const std::vector<double> tabmx32d = dgh::build_mx_tables(p, tab, lay, false);
+    std::vector<float> tabmx32(tabmx32d.begin(), tabmx32d.end());
+    void *d_tab32, *d_tabmx, *d_tabmx32;
     void *d_tab, *d_geo, *d_vtx, *d_perm, *d_el, *d_er, *d_sd, *d_eg, *d_snb, *d_sside, *d_sg, *d_sbc, *d_bcs;
     void *d_ecol, *d_egc;
     const double bc_state0[4] = {1.0, 0.0, 0.0, 1.0 / (gamma - 1.0)};  // until dg_set_boundary_state: at rest, p = 1
     if ((rc = upload(tab.data(), tab.size() * 8, &d_tab)) || (rc = upload(tab32.data(), tab32.size() * 4, &d_tab32)) ||
-        (rc = upload(tabmx.data(), tabmx.size() * 8, &d_tabmx)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
+        (rc = upload(tabmx.data(), tabmx.size() * 8, &d_tabmx)) ||
+        (rc = upload(tabmx32.data(), tabmx32.size() * 4, &d_tabmx32)) || (rc = upload(geo.data(), geo.size() * 8, &d_geo)) ||
         (rc = upload(vtx.data(), vtx.size() * 8, &d_vtx)) || (rc = upload(perm.data(), perm.size() * 4, &d_perm)) ||
         (rc = upload(el.data(), el.size() * 4, &d_el)) || (rc = upload(er.data(), er.size() * 4, &d_er)) ||
         (rc = upload(sd.data(), sd.size() * 4, &d_sd)) || (rc = upload(eg.data(), eg.size() * 8, &d_eg)) ||
@@ -443,6 +447,7 @@ int dg_mesh_create(int p, int64_t n, const double* vxy, const int64_t* nbr, cons
     d.tab = (const double*)d_tab;
     d.tab32 = (const float*)d_tab32;
     d.tabmx = (const double*)d_tabmx;
+    d.tabmx32 = (const float*)d_tabmx32;
     d.geo = (const double*)d_geo;
     d.vtx = (const double*)d_vtx;
     d.perm = (const int*)d_perm;
@@ -519,8 +524,9 @@ int dg_mesh_info(dg_mesh m, dg_info* out)
     out->ws_rhs = m->ws_rhs;
     out->ws_step = m->ws_step;
     out->ws_vjp = m->ws_vjp;
-    out->lanes = m->dev.lanes4 ? 4 : 1;
-    out->stage_fp64 = m->dev.mx ? 16 : out->lanes;
+    const int lanes = m->dev.lanes4 ? 4 : 1;
+    out->stage_fp64 = m->dev.mx ? 16 : lanes;
+    out->stage_mixed = m->dev.mx32 ? 16 : lanes;
     return ok();
 }
 
@@ -850,7 +856,7 @@ int dg_advance(dg_mesh m, double* C, int64_t nsteps, double cfl, double* dt_dev,
     double* part4 = (double*)(w + m->off_part4);
     // the per-64-element minima of the fused step length come from the
     // four-lane and matrix-core stage kernels
-    const bool fused_dt = d.lanes4 || (d.mx && prec == DG_FP64);
+    const bool fused_dt = d.lanes4 || (prec == DG_FP64 ? d.mx : d.mx32);
     if (m->surface != DG_SURFACE_ELEMENTWISE || !fused_dt || m->integrator != DG_RK_SSP3) {
         // separate reduction each step
         for (int64_t k = 0; k < nsteps; ++k) {

@@ -21,7 +21,7 @@ void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
 void side_point(int q, double xi, double* r, double* s);
 std::vector<double> build_tables(int p, TableLayout* lay);
 // the table operands of the matrix-core stage kernel from build_tables' output
-std::vector<double> build_mx_tables(int p, const std::vector<double>& tab, const TableLayout& lay);
+std::vector<double> build_mx_tables(int p, const std::vector<double>& tab, const TableLayout& lay, bool f64);
 
 }  // namespace dgh
 
@@ -35,21 +35,28 @@ namespace dgk {
 constexpr int LANES = 16;
 constexpr int WAVE = 64;
 
-// Table operands of the FP64 matrix-core stage kernel (k_stage_mx): blocks
-// of 64 doubles, one per lane, in the operand order of the 16 x 16 x 4 FP64
-// matrix product (lane 16 k + i holds row i, column k of the 16 x 4 table
-// operand; register r of lane 16 g + j of the product is row 4 r + g).
-// Lane 16 g + j of that kernel holds modes 4 s + g (s < KP) of element j of
-// a 16-element block; point and side-point rows come in tiles of 16, and so
-// do mode rows (row i of mode tile tm is mode 16 tm + i).
+// Table operands of the matrix-core stage kernels (k_stage_mx): blocks of
+// 64 values, one per lane, in the operand order of the 16 x 16 x 4 matrix
+// products (lane 16 k + i holds row i, column k of the 16 x 4 table operand;
+// register r of lane 16 g + j of the product is row mx_row(g, r)).  Lane
+// 16 g + j of that kernel holds modes 4 s + g (s < KP) of element j of a
+// 16-element block; volume and side points come in tiles of 16 rows, and so
+// do modes (row i of mode tile tm is mode mx_mode(tm, i)).
 //   PHI [t][s]      phi_{4s+k} at volume point 16t+i (last point repeated)
-//   DR, DS [tm][t][s']  w dphi/dr, w dphi/ds of mode 16tm+i at volume point
-//                   16t+4s'+k (zero past the last point)
+//   DR, DS [tm][t][s']  w dphi/dr, w dphi/ds of mode mx_mode(tm, i) at
+//                   volume point 16t+mx_row(k, s') (zero past the last point)
 //   PE [ts][s]      phi_{4s+k} at side point 16ts+i (side-major: point k of
 //                   side q is q(p+1)+k; last side point repeated)
-//   LE [tm][ts][s'] Gauss weight times phi of mode 16tm+i at side point
-//                   16ts+4s'+k (zero past the last side point)
+//   LE [tm][ts][s'] Gauss weight times phi of mode mx_mode(tm, i) at side
+//                   point 16ts+mx_row(k, s') (zero past the last side point)
 // Entries of modes >= N_p are zero.
+// Result rows: the FP64 product puts row 4r+g in register r of lane group
+// g, the FP32 product row 4g+r; mx_mode orders the mode rows so that
+// register r of lane group g of mode tile tm is mode 4(4tm+r)+g in both.
+template <bool F64>
+constexpr int mx_row(int g, int r) { return F64 ? 4 * r + g : 4 * g + r; }
+template <bool F64>
+constexpr int mx_mode(int tm, int i) { return F64 ? 16 * tm + i : 4 * (4 * tm + i % 4) + i / 4; }
 struct MxLayout {
     int np, nq, ne, ns, kp, tq, ts, tm;
     int phi, dr, ds, pe, le, blocks;
@@ -82,7 +89,8 @@ struct MeshDev {
     int nedge = 0;
     bool lanes4 = false;  // fused kernels: 4 lanes per element instead of 1
     bool vjp_lanes4 = true;  // adjoint kernels: 4 lanes per element instead of 1
-    bool mx = false;         // FP64 stages on the matrix cores (k_stage_mx) instead of k_stage4
+    bool mx = false;         // FP64 stages on the matrix cores (k_stage_mx)
+    bool mx32 = false;       // mixed-precision stages on the matrix cores (k_stage_mx)
     // domain boundaries: per element 4 bits per side (0 interior, 1 wall,
     // 2 outflow, 3 prescribed state), and the prescribed state (4 doubles)
     const int* side_bc = nullptr;
@@ -91,7 +99,8 @@ struct MeshDev {
     double gamma = 1.4;
     const double* tab = nullptr;      // reference tables (TableLayout)
     const float* tab32 = nullptr;     // the same tables rounded to FP32 (mixed precision)
-    const double* tabmx = nullptr;    // table operands of k_stage_mx (MxLayout)
+    const double* tabmx = nullptr;    // table operands of k_stage_mx (MxLayout), FP64 result layout
+    const float* tabmx32 = nullptr;   // the same for the FP32 products
     const double* geo = nullptr;      // [blk][6][LANES]: adj00 adj01 adj10 adj11 1/detJ r_in
     const double* vtx = nullptr;      // [npad][6] vertices (internal order), setup only
     const int* perm = nullptr;        // internal -> user element id

@@ -28,6 +28,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dg_internal.h"
 
 // 1: the mixed-precision four-lane kernels do their contractions with
@@ -1340,60 +1342,70 @@ __global__ __launch_bounds__(BLOCK) void k_stage4(int n, int npad, const double*
     }
 }
 
-// ---------------------------------------------------------------- FP64 stage on the matrix cores
-// The fused stage of k_stage4 in FP64 with every contraction of eq. (2ddg0)
-// on v_mfma_f64_16x16x4f64: one wavefront per block of 16 elements, the
-// elements are the 16 columns of each product.  Operand layout of that
-// instruction: the 16 x 4 table operand A has row i, column k in lane 16k+i;
-// the 4 x 16 operand B has row k, column j in lane 16k+j; register r of the
-// 16 x 16 result in lane 16g+j is row 4r+g, column j.
+// ---------------------------------------------------------------- stage on the matrix cores, 16 elements per wavefront
+// The fused stage of k_stage4 with every contraction of eq. (2ddg0) on the
+// 16 x 16 x 4 matrix products (v_mfma_f64_16x16x4f64 in FP64,
+// v_mfma_f32_16x16x4f32 in the mixed form): one wavefront per block of 16
+// elements, the elements are the 16 columns of each product.  Operand layout:
+// the 16 x 4 table operand A has row i, column k in lane 16k+i; the 4 x 16
+// operand B has row k, column j in lane 16k+j; register r of the 16 x 16
+// result in lane 16g+j is column j, row mx_row(g, r) = 4r+g for the FP64
+// instruction and 4g+r for the FP32 one.
 // Lane 16g+j holds modes 4s+g (s < KP) of the four variables of element j:
 // the B operands of every contraction over modes (k-step s).
 //   evaluation at 16 points (volume, eq. (volume), or the three sides' Gauss
-//     points, eq. (surface)): register r of lane group g is point 4r+g of
-//     the tile, all four variables at four points per lane, which is what
-//     the fluxes need: no exchange between lanes;
+//     points, eq. (surface)): register r of lane group g is point
+//     mx_row(g, r) of the tile, all four variables at four points per lane,
+//     which is what the fluxes need: no exchange between lanes;
 //   lift back to modes: the lane's fluxes at its points are the B operands,
-//     k-step s' pairing lane group g with point 4s'+g (the table operand is
-//     ordered to match), and register r of lane group g of mode tile tm is
-//     mode 16tm+4r+g = 4(4tm+r)+g: the lane's own modes, so the stage update
-//     needs no exchange either.
+//     k-step s' pairing lane group g with point mx_row(g, s') (the table
+//     operand is ordered to match), and the result rows are ordered so that
+//     register r of lane group g of mode tile tm is mode 4(4tm+r)+g: the
+//     lane's own modes, so the stage update needs no exchange either.
 // The neighbour's trace across side q is the neighbour's side q' at the
 // reversed point; q' differs between the columns, so the neighbour's traces
-// on all three sides are evaluated (one product per side) and each lane
-// picks its points through LDS.  Padded points repeat a real one (finite
+// on all three sides are evaluated (one product per side) and each column
+// keeps the points facing it in LDS.  Padded points repeat a real one (finite
 // fluxes) and carry zero weights; padded modes have zero table entries.
-#ifndef DG_MX_NVH
-#define DG_MX_NVH 2
-#endif
+// Mixed form (T = float): as in k_stage4, FP32 contractions, traces and
+// fluxes; the mean mode accumulated in FP64 from the FP32 fluxes (the lanes
+// of a column add their side points' terms and then each other's); 1/det J
+// and the stage update in FP64 from the FP64 state kept in registers.
 typedef double dx4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ dx4 mfma64(double a, double b, dx4 c)
+typedef float fx4 __attribute__((ext_vector_type(4)));
+template <typename T>
+using mxv = std::conditional_t<sizeof(T) == sizeof(double), dx4, fx4>;
+__device__ __forceinline__ dx4 mfma16(double a, double b, dx4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-
-// at p = 4 the kernel without domain boundaries fits three wavefronts per
-// SIMD without spilling (168 registers) when asked to (the boundary
-// variants and p = 5 would spill; p <= 3 fits three by itself)
-template <int P, bool BC>
-constexpr int mx_waves = P == 4 && !BC ? 3 : 1;
-template <int P, int MODE, bool BC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<P, BC>))) void k_stage_mx(int n, int npad, const double* __restrict__ C,
-                                                    const double* __restrict__ U0, double* __restrict__ out,
-                                                    const double* __restrict__ geo, const int* __restrict__ snb,
-                                                    const int* __restrict__ sside, const double* __restrict__ sgeo,
-                                                    const double* __restrict__ tmx, double gamma, double dt,
-                                                    const double* __restrict__ dt_dev, const double* __restrict__ pin,
-                                                    int pin_count, double cfl, double* __restrict__ dt_store,
-                                                    double* __restrict__ dt_hist, double* __restrict__ pout,
-                                                    StageGen gs, const int* __restrict__ sbc,
-                                                    const double* __restrict__ bcs)
+__device__ __forceinline__ fx4 mfma16(float a, float b, fx4 c)
 {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// at p = 4 the FP64 kernel without domain boundaries fits three wavefronts
+// per SIMD without spilling (168 registers) when asked to (the boundary
+// variants and p = 5 would spill; p <= 3 fits three by itself)
+template <int P, typename T, bool BC>
+constexpr int mx_waves = P == 4 && !BC && sizeof(T) == sizeof(double) ? 3 : 1;
+template <int P, int MODE, typename T, bool BC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<P, T, BC>))) void k_stage_mx(
+    int n, int npad, const double* __restrict__ C, const double* __restrict__ U0, double* __restrict__ out,
+    const double* __restrict__ geo, const int* __restrict__ snb, const int* __restrict__ sside,
+    const double* __restrict__ sgeo, const T* __restrict__ tmx, const double* __restrict__ tab64, double gamma,
+    double dt, const double* __restrict__ dt_dev, const double* __restrict__ pin, int pin_count, double cfl,
+    double* __restrict__ dt_store, double* __restrict__ dt_hist, double* __restrict__ pout, StageGen gs,
+    const int* __restrict__ sbc, const double* __restrict__ bcs)
+{
+    using O = Ord<P>;
+    using V = mxv<T>;
+    constexpr bool F64 = sizeof(T) == sizeof(double);
     constexpr MxLayout X = mx_layout(P);
     constexpr int NP = X.np, NE = X.ne, NS = X.ns, KP = X.kp, TQ = X.tq, TS = X.ts, TM = X.tm;
     constexpr int NW = BLOCK / WAVE;
-    constexpr int NVH = DG_MX_NVH;
-    __shared__ double xs[NW][3][4][NE][LANES];  // neighbour traces facing each side, per wavefront
+    constexpr int NVH = 2;  // neighbour variables gathered together (half the registers of four)
+    __shared__ T xs[NW][3][4][NE][LANES];  // neighbour traces facing each side, per wavefront
     __shared__ double red[NW];
 
     const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -1407,11 +1419,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
     if (lb * NW * LANES >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
     const int e = blk * LANES + j;
     const bool real = e < n;
+    auto row = [&](int r) { return mx_row<F64>(g, r); };
     const double* gp = geo + state_off(e, 6);
-    const double a00 = gp[0], a01 = gp[LANES], a10 = gp[2 * LANES], a11 = gp[3 * LANES], idet = gp[4 * LANES];
-    const double gm1 = gamma - 1.0;
+    const T a00 = T(gp[0]), a01 = T(gp[LANES]), a10 = T(gp[2 * LANES]), a11 = T(gp[3 * LANES]);
+    const double idet = gp[4 * LANES];
+    const T gam = T(gamma), gm1 = T(gamma - 1.0);
     const int base = blk * 4 * NP * LANES + j;
-    const double* tl = tmx + lane;
+    const T* tl = tmx + lane;
     auto A = [&](int b) { return tl[b * WAVE]; };
 
     // own coefficients: c[v][s] = mode 4s+g of variable v (a padded mode
@@ -1422,37 +1436,37 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
 #pragma unroll
         for (int s = 0; s < KP; ++s) c[v][s] = C[base + (v * NP + min(4 * s + g, NP - 1)) * LANES];
 
-    dx4 acc[4][TM];
+    V acc[4][TM];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int t = 0; t < TM; ++t) acc[v][t] = dx4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < TM; ++t) acc[v][t] = V{0, 0, 0, 0};
 
     // volume integral, eq. (volume)
 #pragma unroll
     for (int tq = 0; tq < TQ; ++tq) {
-        dx4 u[4];
+        V u[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) u[v] = dx4{0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < 4; ++v) u[v] = V{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KP; ++s) {
-            const double a = A(X.phi + tq * KP + s);
+            const T a = A(X.phi + tq * KP + s);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) u[v] = mfma64(a, c[v][s], u[v]);
+            for (int v = 0; v < 4; ++v) u[v] = mfma16(a, T(c[v][s]), u[v]);
         }
         // the flux at the lane's point r is k-step r of the lift
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double U[4] = {u[0][r], u[1][r], u[2][r], u[3][r]};
-            double Fx[4], Fy[4];
-            euler_flux<double>(gm1, U, Fx, Fy);
+            const T U[4] = {u[0][r], u[1][r], u[2][r], u[3][r]};
+            T Fx[4], Fy[4];
+            euler_flux<T>(gm1, U, Fx, Fy);
 #pragma unroll
             for (int tm = 0; tm < TM; ++tm) {
-                const double ar = A(X.dr + (tm * TQ + tq) * 4 + r), as = A(X.ds + (tm * TQ + tq) * 4 + r);
+                const T ar = A(X.dr + (tm * TQ + tq) * 4 + r), as = A(X.ds + (tm * TQ + tq) * 4 + r);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    acc[v][tm] = mfma64(ar, a00 * Fx[v] + a01 * Fy[v], acc[v][tm]);
-                    acc[v][tm] = mfma64(as, a10 * Fx[v] + a11 * Fy[v], acc[v][tm]);
+                    acc[v][tm] = mfma16(ar, a00 * Fx[v] + a01 * Fy[v], acc[v][tm]);
+                    acc[v][tm] = mfma16(as, a10 * Fx[v] + a11 * Fy[v], acc[v][tm]);
                 }
             }
         }
@@ -1461,37 +1475,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
     // surface integral, eq. (surface): the neighbours' traces first, side
     // by side; each column keeps, in LDS, the p+1 points of its neighbour's
     // side that face it, in its own order (reversed), so no lane holds
-    // neighbour values across the sides (register r of tile ts of lane
-    // group g is side point 16ts+4r+g, side-major)
+    // neighbour values across the sides (register r of tile ts is side point
+    // 16ts+row(r), side-major)
     const int sides = sside[state_off(e, 1)];
     const int* const nb = snb + state_off(e, 3);
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
         const int nbase = state_off(nb[q * LANES], 4 * NP);
         const int qn = (sides >> (2 * q)) & 3;
-        // two variables at a time (half the registers of all four)
 #pragma unroll
         for (int v0 = 0; v0 < 4; v0 += NVH) {
-            double cn[NVH][KP];
+            T cn[NVH][KP];
 #pragma unroll
             for (int v = 0; v < NVH; ++v)
 #pragma unroll
                 for (int s = 0; s < KP; ++s)
-                    cn[v][s] = C[nbase + ((v0 + v) * NP + min(4 * s + g, NP - 1)) * LANES];
+                    cn[v][s] = T(C[nbase + ((v0 + v) * NP + min(4 * s + g, NP - 1)) * LANES]);
 #pragma unroll
             for (int ts = 0; ts < TS; ++ts) {
-                dx4 tn[NVH];
+                V tn[NVH];
 #pragma unroll
-                for (int v = 0; v < NVH; ++v) tn[v] = dx4{0.0, 0.0, 0.0, 0.0};
+                for (int v = 0; v < NVH; ++v) tn[v] = V{0, 0, 0, 0};
 #pragma unroll
                 for (int s = 0; s < KP; ++s) {
-                    const double a = A(X.pe + ts * KP + s);
+                    const T a = A(X.pe + ts * KP + s);
 #pragma unroll
-                    for (int v = 0; v < NVH; ++v) tn[v] = mfma64(a, cn[v][s], tn[v]);
+                    for (int v = 0; v < NVH; ++v) tn[v] = mfma16(a, cn[v][s], tn[v]);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int k = 16 * ts + 4 * r + g - qn * NE;  // point of the neighbour's side qn
+                    const int k = 16 * ts + row(r) - qn * NE;  // point of the neighbour's side qn
                     if (k >= 0 && k < NE) {
 #pragma unroll
                         for (int v = 0; v < NVH; ++v) xs[w][q][v0 + v][NE - 1 - k][j] = tn[v][r];
@@ -1506,42 +1519,57 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
     // by minus the half side length (the Gauss weights are in the table),
     // and the lift
     const int bcv = BC ? sbc[state_off(e, 1)] : 0;
-    double G[4];
+    T G[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) G[v] = BC ? bcs[v] : 0.0;
+    for (int v = 0; v < 4; ++v) G[v] = BC ? T(bcs[v]) : T(0);
+    double acc0[4] = {0.0, 0.0, 0.0, 0.0};  // mixed form: the mean mode in FP64
 #pragma unroll
     for (int ts = 0; ts < TS; ++ts) {
-        dx4 ul[4];
+        V ul[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ul[v] = dx4{0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < 4; ++v) ul[v] = V{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KP; ++s) {
-            const double a = A(X.pe + ts * KP + s);
+            const T a = A(X.pe + ts * KP + s);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ul[v] = mfma64(a, c[v][s], ul[v]);
+            for (int v = 0; v < 4; ++v) ul[v] = mfma16(a, T(c[v][s]), ul[v]);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int sp = 16 * ts + 4 * r + g;
+            const int sp = 16 * ts + row(r);
             const int q = min(sp / NE, 2);
             const bool pad = sp >= NS;
             const int go = state_off(e, 9) + 3 * q * LANES;
-            const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
+            const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
+            const double hl = sgeo[go + 2 * LANES];
             const int k = min(sp - q * NE, NE - 1);
-            double UL[4], UR[4], F[4];
+            T UL[4], UR[4], F[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 UL[v] = ul[v][r];
                 UR[v] = pad ? UL[v] : xs[w][q][v][k][j];
             }
-            if constexpr (BC) ghost_state<double>((bcv >> (4 * q)) & 15, UL, nx, ny, G, UR);
-            llf<double>(gamma, gm1, UL, UR, nx, ny, F);
+            if constexpr (BC) ghost_state<T>((bcv >> (4 * q)) & 15, UL, nx, ny, G, UR);
+            llf<T>(gam, gm1, UL, UR, nx, ny, F);
+            if constexpr (!F64) {
+                const double w0 = pad ? 0.0 : -hl * tab64[O::GW + k] * tab64[O::PHS + (q * NE + k) * NP];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc0[v] = fma(w0, double(F[v]), acc0[v]);
+            }
 #pragma unroll
             for (int tm = 0; tm < TM; ++tm) {
-                const double a = A(X.le + (tm * TS + ts) * 4 + r);
+                const T a = A(X.le + (tm * TS + ts) * 4 + r);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[v][tm] = mfma64(a, -hl * F[v], acc[v][tm]);
+                for (int v = 0; v < 4; ++v) acc[v][tm] = mfma16(a, T(-hl) * F[v], acc[v][tm]);
             }
+        }
+    }
+    if constexpr (!F64) {
+        // the column's four lanes add their terms of the mean mode
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            acc0[v] += __shfl_xor(acc0[v], 16);
+            acc0[v] += __shfl_xor(acc0[v], 32);
         }
     }
 
@@ -1564,7 +1592,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
             const int jm = 4 * s + g;
             if (jm < NP) {
                 const int x = base + (v * NP + jm) * LANES;
-                const double L = idet * acc[v][s / 4][s % 4];
+                const double a = (!F64 && s == 0 && g == 0) ? acc0[v] : double(acc[v][s / 4][s % 4]);
+                const double L = idet * a;
                 double val;
                 if (!real) {
                     val = 0.0;
@@ -2348,15 +2377,15 @@ struct Launch {
     {
         // (one lane per element only up to p = 3: from p = 4 on its values
         // exceed a lane's registers, and the library refuses it)
-        if constexpr (sizeof(T) == sizeof(double)) {
-            if (m.mx) {
-                dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
-                k_stage_mx<P, MODE, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q,
-                                                             m.side_g, m.tabmx, m.gamma, dt, dt_dev, fz.pin,
-                                                             fz.pin_count, fz.cfl, fz.dt_store, fz.dt_hist, fz.pout,
-                                                             gs, m.side_bc, m.bc_state);
-                return;
-            }
+        constexpr bool F64 = sizeof(T) == sizeof(double);
+        if (F64 ? m.mx : m.mx32) {
+            dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
+            const T* tmx = F64 ? (const T*)m.tabmx : (const T*)m.tabmx32;
+            k_stage_mx<P, MODE, T, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, U0, out, m.geo, m.side_nb, m.side_q,
+                                                            m.side_g, tmx, m.tab, m.gamma, dt, dt_dev, fz.pin,
+                                                            fz.pin_count, fz.cfl, fz.dt_store, fz.dt_hist, fz.pout,
+                                                            gs, m.side_bc, m.bc_state);
+            return;
         }
         if (P >= 4 || m.lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);

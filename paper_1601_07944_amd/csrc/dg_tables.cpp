@@ -334,8 +334,10 @@ std::vector<double> build_tables(int p, TableLayout* lay)
     return t;
 }
 
-std::vector<double> build_mx_tables(int p, const std::vector<double>& t, const TableLayout& L)
+std::vector<double> build_mx_tables(int p, const std::vector<double>& t, const TableLayout& L, bool f64)
 {
+    auto row = [&](int g, int r) { return f64 ? dgk::mx_row<true>(g, r) : dgk::mx_row<false>(g, r); };
+    auto mode = [&](int tm, int i) { return f64 ? dgk::mx_mode<true>(tm, i) : dgk::mx_mode<false>(tm, i); };
     const dgk::MxLayout x = dgk::mx_layout(p);
     std::vector<double> o((size_t)x.blocks * 64, 0.0);
     auto put = [&](int blk, int lane, double v) { o[(size_t)blk * 64 + lane] = v; };
@@ -349,7 +351,7 @@ std::vector<double> build_mx_tables(int p, const std::vector<double>& t, const T
         for (int tm = 0; tm < x.tm; ++tm)
             for (int tq = 0; tq < x.tq; ++tq)
                 for (int s = 0; s < 4; ++s) {
-                    const int j = 16 * tm + i, pt = 16 * tq + 4 * s + k, b = (tm * x.tq + tq) * 4 + s;
+                    const int j = mode(tm, i), pt = 16 * tq + row(k, s), b = (tm * x.tq + tq) * 4 + s;
                     const bool in = j < x.np && pt < x.nq;
                     put(x.dr + b, lane, in ? t[L.drw + pt * x.np + j] : 0.0);
                     put(x.ds + b, lane, in ? t[L.dsw + pt * x.np + j] : 0.0);
@@ -362,7 +364,7 @@ std::vector<double> build_mx_tables(int p, const std::vector<double>& t, const T
         for (int tm = 0; tm < x.tm; ++tm)
             for (int ts = 0; ts < x.ts; ++ts)
                 for (int s = 0; s < 4; ++s) {
-                    const int j = 16 * tm + i, sp = 16 * ts + 4 * s + k;
+                    const int j = mode(tm, i), sp = 16 * ts + row(k, s);
                     const bool in = j < x.np && sp < x.ns;
                     put(x.le + (tm * x.ts + ts) * 4 + s, lane, in ? t[L.gw + sp % x.ne] * t[L.phs + sp * x.np + j] : 0.0);
                 }

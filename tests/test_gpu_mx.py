@@ -208,8 +208,9 @@ def test_automatic_choice(p, auto_mx):
     vec.set_lanes(4)
     four = B.DGMesh.from_mesh(mesh, p)
     four.set_lanes(4)
-    assert auto.kernel_choice() == ((16 if auto_mx else 4), 4)
-    assert forced.kernel_choice() == (16, 4) and vec.kernel_choice() == (4, 4) and four.kernel_choice() == (4, 4)
+    k = 16 if auto_mx else 4
+    assert auto.kernel_choice() == (k, k)
+    assert forced.kernel_choice() == (16, 16) and vec.kernel_choice() == (4, 4) and four.kernel_choice() == (4, 4)
     Cg = auto.pack(dev(C))
     Ra, Rm, Rv, R4 = auto.rhs(Cg), forced.rhs(Cg), vec.rhs(Cg), four.rhs(Cg)
     torch.cuda.synchronize()
@@ -217,3 +218,75 @@ def test_automatic_choice(p, auto_mx):
     assert torch.equal(R4, Rv)
     for R in (Ra, Rm, Rv):
         assert rel_l2(auto.unpack(R).cpu().numpy(), orc.rhs(C)) <= TOL
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_mixed_rhs_bound_and_conservation(p):
+    # the mixed form on the matrix cores: within the mixed bound of the FP64
+    # oracle (3e-5 relative L2 for one right-hand side), and the element
+    # means conservative to FP64 rounding (bitwise equal FP32 edge fluxes)
+    mesh = W.delaunay_mesh(900, 4)
+    orc = O.Oracle(mesh, p)
+    C = orc.project(W.density_jump)
+    dm = mx_mesh(mesh, p)
+    case(f"dg_rhs DG_MIXED matrix cores p={p} N={mesh.n_elem}")
+    R = dm.unpack(dm.rhs(dm.pack(dev(C)), prec=1)).cpu().numpy()
+    err = rel_l2(R, orc.rhs(C))
+    print(f"mixed matrix-core rhs p={p} rel L2 {err:.2e}", file=sys.stderr, flush=True)
+    assert err <= 3e-5
+    terms = orc.det()[:, None] * R[:, :, 0]
+    assert np.all(np.abs(terms.sum(0)) < 1e-13 * np.abs(terms).sum(0))
+
+
+@pytest.mark.parametrize("p", [1, 3, 4, 5])
+def test_mixed_100_steps(p):
+    import torch
+
+    mesh = W.delaunay_mesh(2000, 2)
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.smooth_density)
+    dm = mx_mesh(mesh, p)
+    Cg = dm.pack(dev(C0))
+    cfl = 0.3 / (2 * p + 1)
+    case(f"dg_rk_step DG_MIXED matrix cores p={p} 100 steps N={mesh.n_elem}")
+    Co = C0
+    tot0 = (orc.det()[:, None] * C0[:, :, 0]).sum(0)
+    for _ in range(100):
+        dt, _ = orc.max_dt(Co, cfl)
+        Co = orc.rk3_step(Co, dt)
+        dm.rk_step(Cg, dt, prec=1)
+    got = dm.unpack(Cg).cpu().numpy()
+    torch.cuda.synchronize()
+    err = rel_l2(got, Co)
+    print(f"mixed matrix-core 100 steps p={p} rel L2 {err:.2e}", file=sys.stderr, flush=True)
+    assert err <= 1e-5
+    tot = (orc.det()[:, None] * got[:, :, 0]).sum(0)
+    assert np.all(np.abs(tot - tot0) <= 1e-12 * np.abs(tot0))
+
+
+@pytest.mark.parametrize("p", [2, 4])
+@pytest.mark.parametrize("kind", sorted(BOXES))
+def test_mixed_boundaries_and_fused_step_length(kind, p):
+    # mixed form with domain boundaries: one right-hand side within 3e-5, and
+    # dg_advance (step length fused into the stages) equal to max_dt + rk_step
+    import torch
+
+    mesh = W.box_mesh(14, 12, 1.0, 1.0, 0.2, 4, bc=BOXES[kind])
+    orc = O.Oracle(mesh, p)
+    orc.set_bc_state(U_FAR)
+    dm = mx_mesh(mesh, p)
+    dm.set_boundary_state(U_FAR)
+    C = orc.project(flow)
+    case(f"DG_MIXED matrix cores box={kind} p={p}")
+    got = dm.unpack(dm.rhs(dm.pack(dev(C)), prec=1)).cpu().numpy()
+    assert rel_l2(got, orc.rhs(C)) <= 3e-5
+    C0 = dm.pack(dev(C))
+    cfl = 0.3 / (2 * p + 1)
+    Ca = C0.clone()
+    dm.advance(Ca, 4, cfl, prec=1)
+    Cs = C0.clone()
+    for _ in range(4):
+        dt_dev, _ = dm.max_dt(Cs, cfl)
+        dm.rk_step(Cs, dt_dev=dt_dev, prec=1)
+    torch.cuda.synchronize()
+    assert torch.equal(Ca, Cs)
