@@ -1442,6 +1442,25 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
 #pragma unroll
         for (int t = 0; t < TM; ++t) acc[v][t] = V{0, 0, 0, 0};
 
+    // the neighbours' coefficients, two variables of one side at a time:
+    // where registers allow (mixed form, FP64 up to p = 3), each pair is
+    // gathered one step ahead of its use and the first before the volume
+    // integral (FP64 at p = 4, 5 would lose a wavefront per SIMD to it)
+    constexpr bool PIPE = !F64 || P <= 3;
+    constexpr int NT = 3 * (4 / NVH);  // (side, variable pair) steps
+    const int sides = sside[state_off(e, 1)];
+    const int* const nb = snb + state_off(e, 3);
+    auto gather = [&](int t, T (&dst)[NVH][KP]) {
+        const int q = t / (4 / NVH), v0 = (t % (4 / NVH)) * NVH;
+        const int nbase = state_off(nb[q * LANES], 4 * NP);
+#pragma unroll
+        for (int v = 0; v < NVH; ++v)
+#pragma unroll
+            for (int s = 0; s < KP; ++s) dst[v][s] = T(C[nbase + ((v0 + v) * NP + min(4 * s + g, NP - 1)) * LANES]);
+    };
+    T cnx[NVH][KP];
+    if constexpr (PIPE) gather(0, cnx);
+
     // volume integral, eq. (volume)
 #pragma unroll
     for (int tq = 0; tq < TQ; ++tq) {
@@ -1477,40 +1496,48 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
     // side that face it, in its own order (reversed), so no lane holds
     // neighbour values across the sides (register r of tile ts is side point
     // 16ts+row(r), side-major)
-    const int sides = sside[state_off(e, 1)];
-    const int* const nb = snb + state_off(e, 3);
-#pragma unroll 1
-    for (int q = 0; q < 3; ++q) {
-        const int nbase = state_off(nb[q * LANES], 4 * NP);
+    // the neighbour's traces at all its side points for step t, and the
+    // points facing this column into LDS
+    auto traces = [&](int t, const T (&cn)[NVH][KP]) {
+        const int q = t / (4 / NVH), v0 = (t % (4 / NVH)) * NVH;
         const int qn = (sides >> (2 * q)) & 3;
 #pragma unroll
-        for (int v0 = 0; v0 < 4; v0 += NVH) {
+        for (int ts = 0; ts < TS; ++ts) {
+            V tn[NVH];
+#pragma unroll
+            for (int v = 0; v < NVH; ++v) tn[v] = V{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KP; ++s) {
+                const T a = A(X.pe + ts * KP + s);
+#pragma unroll
+                for (int v = 0; v < NVH; ++v) tn[v] = mfma16(a, cn[v][s], tn[v]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 16 * ts + row(r) - qn * NE;  // point of the neighbour's side qn
+                if (k >= 0 && k < NE) {
+#pragma unroll
+                    for (int v = 0; v < NVH; ++v) xs[w][q][v0 + v][NE - 1 - k][j] = tn[v][r];
+                }
+            }
+        }
+    };
+    if constexpr (PIPE) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
             T cn[NVH][KP];
 #pragma unroll
             for (int v = 0; v < NVH; ++v)
 #pragma unroll
-                for (int s = 0; s < KP; ++s)
-                    cn[v][s] = T(C[nbase + ((v0 + v) * NP + min(4 * s + g, NP - 1)) * LANES]);
-#pragma unroll
-            for (int ts = 0; ts < TS; ++ts) {
-                V tn[NVH];
-#pragma unroll
-                for (int v = 0; v < NVH; ++v) tn[v] = V{0, 0, 0, 0};
-#pragma unroll
-                for (int s = 0; s < KP; ++s) {
-                    const T a = A(X.pe + ts * KP + s);
-#pragma unroll
-                    for (int v = 0; v < NVH; ++v) tn[v] = mfma16(a, cn[v][s], tn[v]);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int k = 16 * ts + row(r) - qn * NE;  // point of the neighbour's side qn
-                    if (k >= 0 && k < NE) {
-#pragma unroll
-                        for (int v = 0; v < NVH; ++v) xs[w][q][v0 + v][NE - 1 - k][j] = tn[v][r];
-                    }
-                }
-            }
+                for (int s = 0; s < KP; ++s) cn[v][s] = cnx[v][s];
+            if (t + 1 < NT) gather(t + 1, cnx);
+            traces(t, cn);
+        }
+    } else {
+#pragma unroll 1
+        for (int t = 0; t < NT; ++t) {
+            gather(t, cnx);
+            traces(t, cnx);
         }
     }
     wave_sync();
