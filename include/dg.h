@@ -431,6 +431,26 @@ int dg_timing_read(dg_mesh m, double* ms, int64_t* count, int n);
  * written (> 0), or a negative dg_status. */
 int64_t dg_reference_tables(int p, double* out, int64_t cap);
 
+/* Host-only: the table operands of the matrix-core stage kernels
+ * (dg_set_matrix_cores), for checking them on a machine without a GPU: the
+ * 16 x 4 operands of the 16 x 16 x 4 products as blocks of 64 values in lane
+ * order (lane 16k+i holds row i, column k).  fp64 != 0: the FP64 kernel's
+ * order (register r of lane group g of a product is row 4r+g), 0: the FP32
+ * kernel's (row 4g+r; the kernel uses these values rounded to FP32).  With
+ * N_p modes, N_q volume points, p+1 Gauss points per side, KP = ceil(N_p/4),
+ * TQ = ceil(N_q/16), TS = ceil(3(p+1)/16), TM = ceil(KP/4), row(g, r) as
+ * above and mode(tm, i) = 16tm+i (FP64) or 4(4tm+i%4)+i/4 (FP32), the
+ * blocks are, in this order (entries of modes >= N_p zero):
+ *   [t][s] (TQ x KP): phi_{4s+k} at volume point min(16t+i, N_q-1);
+ *   [tm][t][s'] (TM x TQ x 4), twice: w dphi/dr, then w dphi/ds, of mode
+ *     mode(tm, i) at volume point 16t+row(k, s') (zero past N_q);
+ *   [ts][s] (TS x KP): phi_{4s+k} at side point min(16ts+i, 3(p+1)-1), side
+ *     points side-major (point k of side q is q(p+1)+k);
+ *   [tm][ts][s'] (TM x TS x 4): Gauss weight times phi of mode mode(tm, i) at
+ *     side point 16ts+row(k, s') (zero past the last side point).
+ * Returns the number of doubles written (> 0), or a negative dg_status. */
+int64_t dg_matrix_core_tables(int p, int fp64, double* out, int64_t cap);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* dg_last_error(void);
 

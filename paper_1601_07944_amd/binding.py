@@ -61,6 +61,7 @@ EXPORTS = [
     "dg_timing_enable",
     "dg_timing_read",
     "dg_reference_tables",
+    "dg_matrix_core_tables",
     "dg_last_error",
 ]
 
@@ -139,6 +140,8 @@ def load(path: str = LIB_PATH):
     lib.dg_timing_read.argtypes = [_vp, _dp, ctypes.POINTER(i64), i32]
     lib.dg_reference_tables.argtypes = [i32, _dp, i64]
     lib.dg_reference_tables.restype = i64
+    lib.dg_matrix_core_tables.argtypes = [i32, i32, _dp, i64]
+    lib.dg_matrix_core_tables.restype = i64
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or i32
     _lib = lib
@@ -188,6 +191,16 @@ def reference_tables(p: int) -> dict:
     out["phi_side"] = take(3 * ne * np_).reshape(3, ne, np_)
     assert o == n
     return out
+
+
+def matrix_core_tables(p: int, fp64: bool) -> "np.ndarray":
+    """Host-only: the matrix-core kernels' table operands, [blocks][64]."""
+    cap = 1 << 16
+    buf = np.zeros(cap)
+    n = load().dg_matrix_core_tables(p, 1 if fp64 else 0, buf.ctypes.data_as(_dp), cap)
+    if n < 0:
+        _check(int(n))
+    return buf[:n].reshape(-1, 64).copy()
 
 
 def _stream(stream=None):

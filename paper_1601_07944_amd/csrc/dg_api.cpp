@@ -1078,6 +1078,18 @@ int dg_timing_read(dg_mesh m, double* ms, int64_t* count, int n)
     return rc == DG_OK ? ok() : rc;
 }
 
+int64_t dg_matrix_core_tables(int p, int fp64, double* out, int64_t cap)
+{
+    if (p < 1 || p > 5) return fail(DG_EORDER, "order p=%d outside 1..5", p);
+    if (!out) return fail(DG_EINVAL, "null argument");
+    dgh::TableLayout lay;
+    const std::vector<double> tab = dgh::build_tables(p, &lay);
+    const std::vector<double> mx = dgh::build_mx_tables(p, tab, lay, fp64 != 0);
+    if (cap < (int64_t)mx.size()) return fail(DG_EINVAL, "capacity %lld < %lld", (long long)cap, (long long)mx.size());
+    std::copy(mx.begin(), mx.end(), out);
+    return (int64_t)mx.size();
+}
+
 int64_t dg_reference_tables(int p, double* out, int64_t cap)
 {
     if (p < 1 || p > 5) return fail(DG_EORDER, "order p=%d outside 1..5", p);
