@@ -126,6 +126,16 @@ def stage_kernel(dm, prec) -> int:
     return fp64 if prec == B.DG_FP64 else mixed
 
 
+def adjoint_kernel_name(dm, p):
+    k = dm.adjoint_kernel()
+    what = "adjoint of the fused RHS / SSP-RK3 stage"
+    if k == 16:
+        return f"k_stage_vjp_mx<{p}, 1..3> ({what}, 16 x 16 x 4 matrix products, 16 elements per wavefront)"
+    if k == 4:
+        return f"k_stage_vjp4<{p}, 1..3> ({what}, 4 lanes per element)"
+    return f"k_stage_vjp<{p}, 1..3> ({what}, 1 lane per element)"
+
+
 def stage_kernel_name(dm, p, prec=0):
     k = stage_kernel(dm, prec)
     t = "double" if prec == 0 else "float"
@@ -399,6 +409,8 @@ def adjoint_131072(dev):
     r = adjoint_ratio(dm, C0, dt, 200, 20)
     r["workload"] = ("smooth density wave, periodic unit square, 256x256x2 = 131,072 triangles jittered by 0.2h "
                      "(seed 3), p=2, FP64, fixed dt")
+    r["adjoint_kernel"] = adjoint_kernel_name(dm, p)
+    r["forward_kernel"] = stage_kernel_name(dm, p)
     dm.close()
     return r
 
@@ -675,7 +687,9 @@ def main():
     }
     if not args.quick:
         section(out, "adjoint_forward_ratio", lambda: dict(adjoint_ratio(dm, C0, dt_host, 50, 20),
-                                                           workload="the headline workload, fixed dt"))
+                                                           workload="the headline workload, fixed dt",
+                                                           adjoint_kernel=adjoint_kernel_name(dm, p),
+                                                           forward_kernel=stage_kernel_name(dm, p)))
     dm.close()
     del C0, dm
     torch.cuda.empty_cache()

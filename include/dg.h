@@ -105,6 +105,7 @@ typedef struct {
     int stage_fp64;     /* element-wise stage kernel of the current choice in FP64: 1 or 4 lanes
                            per element or 16 (16 x 16 x 4 matrix products, 16 elements per wavefront) */
     int stage_mixed;    /* the same for DG_MIXED */
+    int adjoint;        /* adjoint stage kernel (dg_rhs_vjp, dg_rk_step_vjp): 1, 4 or 16, as above */
 } dg_info;
 
 /* Checks a mesh without touching the GPU (no HIP call).  Arguments as for
@@ -395,8 +396,10 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes);
  * vector-ALU kernels chosen by dg_set_lanes_per_element; -1 (the default)
  * automatic: the matrix cores at p = 4 at every size and at p = 3 and 5 up
  * to DG_LANES4_MAX_ELEMENTS elements, as long as the lane count is automatic
- * too (an explicit 1 or 4 keeps the vector-ALU kernels).  The adjoint is
- * unaffected.  Same result to rounding.  Returns DG_EINVAL for other values
+ * too (an explicit 1 or 4 keeps the vector-ALU kernels).  The adjoint
+ * (dg_rhs_vjp, dg_rk_step_vjp) has a matrix-core kernel of the same layout:
+ * used with on = 1, and automatically at p = 3 and 4 when the lane count is
+ * automatic.  Same result to rounding.  Returns DG_EINVAL for other values
  * of on. */
 int dg_set_matrix_cores(dg_mesh m, int on);
 
@@ -447,7 +450,14 @@ int64_t dg_reference_tables(int p, double* out, int64_t cap);
  *   [ts][s] (TS x KP): phi_{4s+k} at side point min(16ts+i, 3(p+1)-1), side
  *     points side-major (point k of side q is q(p+1)+k);
  *   [tm][ts][s'] (TM x TS x 4): Gauss weight times phi of mode mode(tm, i) at
- *     side point 16ts+row(k, s') (zero past the last side point).
+ *     side point 16ts+row(k, s') (zero past the last side point);
+ * and for the adjoint kernel:
+ *   [t][s] (TQ x KP), twice: w dphi/dr, then w dphi/ds, of mode 4s+k at
+ *     volume point min(16t+i, N_q-1);
+ *   [tm][t][s'] (TM x TQ x 4): phi of mode mode(tm, i) at volume point
+ *     16t+row(k, s') (zero past N_q);
+ *   [tm][ts][s'] (TM x TS x 4): phi of mode mode(tm, i) at side point
+ *     16ts+row(k, s') (zero past the last side point).
  * Returns the number of doubles written (> 0), or a negative dg_status. */
 int64_t dg_matrix_core_tables(int p, int fp64, double* out, int64_t cap);
 

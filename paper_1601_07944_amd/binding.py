@@ -88,6 +88,7 @@ class dg_info(ctypes.Structure):
         ("n_colours", ctypes.c_int64),
         ("stage_fp64", ctypes.c_int),
         ("stage_mixed", ctypes.c_int),
+        ("adjoint", ctypes.c_int),
     ]
 
 
@@ -370,6 +371,13 @@ class DGMesh:
         info = dg_info()
         _check(self._lib.dg_mesh_info(self._h, ctypes.byref(info)))
         return info.stage_fp64, info.stage_mixed
+
+    def adjoint_kernel(self):
+        """Adjoint stage kernel of the current choice: 1 or 4 lanes per
+        element, or 16 (16 x 16 x 4 matrix products)."""
+        info = dg_info()
+        _check(self._lib.dg_mesh_info(self._h, ctypes.byref(info)))
+        return info.adjoint
 
     def set_matrix_cores(self, on):
         """FP64 stages with their contractions on the matrix cores: True, False,

@@ -49,6 +49,13 @@ constexpr int WAVE = 64;
 //                   side q is q(p+1)+k; last side point repeated)
 //   LE [tm][ts][s'] Gauss weight times phi of mode mx_mode(tm, i) at side
 //                   point 16ts+mx_row(k, s') (zero past the last side point)
+// and, for the adjoint (the transposed contractions):
+//   DRE, DSE [t][s] w dphi/dr, w dphi/ds of mode 4s+k at volume point
+//                   16t+i (last point repeated)
+//   PHL [tm][t][s'] phi of mode mx_mode(tm, i) at volume point
+//                   16t+mx_row(k, s') (zero past the last point)
+//   PEL [tm][ts][s'] phi of mode mx_mode(tm, i) at side point
+//                   16ts+mx_row(k, s') (zero past the last side point)
 // Entries of modes >= N_p are zero.
 // Result rows: the FP64 product puts row 4r+g in register r of lane group
 // g, the FP32 product row 4g+r; mx_mode orders the mode rows so that
@@ -59,7 +66,7 @@ template <bool F64>
 constexpr int mx_mode(int tm, int i) { return F64 ? 16 * tm + i : 4 * (4 * tm + i % 4) + i / 4; }
 struct MxLayout {
     int np, nq, ne, ns, kp, tq, ts, tm;
-    int phi, dr, ds, pe, le, blocks;
+    int phi, dr, ds, pe, le, dre, dse, phl, pel, blocks;
 };
 constexpr MxLayout mx_layout(int p)
 {
@@ -77,7 +84,11 @@ constexpr MxLayout mx_layout(int p)
     x.ds = x.dr + x.tm * x.tq * 4;
     x.pe = x.ds + x.tm * x.tq * 4;
     x.le = x.pe + x.ts * x.kp;
-    x.blocks = x.le + x.tm * x.ts * 4;
+    x.dre = x.le + x.tm * x.ts * 4;
+    x.dse = x.dre + x.tq * x.kp;
+    x.phl = x.dse + x.tq * x.kp;
+    x.pel = x.phl + x.tm * x.tq * 4;
+    x.blocks = x.pel + x.tm * x.ts * 4;
     return x;
 }
 
@@ -91,6 +102,7 @@ struct MeshDev {
     bool vjp_lanes4 = true;  // adjoint kernels: 4 lanes per element instead of 1
     bool mx = false;         // FP64 stages on the matrix cores (k_stage_mx)
     bool mx32 = false;       // mixed-precision stages on the matrix cores (k_stage_mx)
+    bool mx_vjp = false;     // adjoint stages on the matrix cores (k_stage_vjp_mx)
     // domain boundaries: per element 4 bits per side (0 interior, 1 wall,
     // 2 outflow, 3 prescribed state), and the prescribed state (4 doubles)
     const int* side_bc = nullptr;

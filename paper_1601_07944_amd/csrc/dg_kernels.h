@@ -2185,6 +2185,231 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp4(int n, int npad, const dou
     }
 }
 
+// The adjoint of k_stage_mx (modes as k_stage_vjp), FP64, one wavefront per
+// 16-element block with every contraction a 16 x 16 x 4 product: at the
+// volume points the state (phi) and the scaled cotangent's flux cotangents
+// (w grad phi, transposed tables) are evaluated, flux_vjp gives the
+// point's state cotangent and phi lifts it back (transposed layout); at the
+// side points the traces of the state and of the scaled cotangent, own and
+// the neighbour's (through LDS as in k_stage_mx), give the numerical flux's
+// cotangent, llf_vjp_left (llf_vjp_side on boundary sides) the state
+// cotangent, and the side table lifts it.  Lane layout and result order as
+// in k_stage_mx.
+template <int P, int MODE, bool BC>
+__global__ __launch_bounds__(BLOCK) void k_stage_vjp_mx(int n, int npad, const double* __restrict__ C,
+                                                        const double* __restrict__ Rb, const double* __restrict__ X,
+                                                        const double* __restrict__ Y, double* __restrict__ out,
+                                                        const double* __restrict__ geo, const int* __restrict__ snb,
+                                                        const int* __restrict__ sside,
+                                                        const double* __restrict__ sgeo,
+                                                        const double* __restrict__ tmx,
+                                                        const double* __restrict__ tab, double gamma, double dt,
+                                                        const double* __restrict__ dt_dev,
+                                                        const int* __restrict__ sbc, const double* __restrict__ bcs)
+{
+    using O = Ord<P>;
+    constexpr MxLayout L = mx_layout(P);
+    constexpr int NP = L.np, NE = L.ne, NS = L.ns, KP = L.kp, TQ = L.tq, TS = L.ts, TM = L.tm;
+    constexpr int NW = BLOCK / WAVE;
+    constexpr int NVH = 2;
+    __shared__ double xc[NW][3][4][NE][LANES];  // the neighbours' state traces facing each side
+    __shared__ double xr[NW][3][4][NE][LANES];  // and their scaled cotangents' traces
+
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE, j = lane % 16, g = lane / 16;
+    const int blk = lb * NW + w;
+    if (lb * NW * LANES >= npad) return;  // whole workgroups leave together (npad % 64 == 0)
+    const int e = blk * LANES + j;
+    const bool real = e < n;
+    auto row = [&](int r) { return mx_row<true>(g, r); };
+    const double* gp = geo + state_off(e, 6);
+    const double a00 = gp[0], a01 = gp[LANES], a10 = gp[2 * LANES], a11 = gp[3 * LANES], idet = gp[4 * LANES];
+    const double gm1 = gamma - 1.0;
+    const int base = blk * 4 * NP * LANES + j;
+    const double* tl = tmx + lane;
+    auto A = [&](int b) { return tl[b * WAVE]; };
+
+    // own state and right-hand-side cotangent scaled by 1/det J, modes 4s+g
+    double c[4][KP], rs[4][KP];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int s = 0; s < KP; ++s) {
+            const int x = base + (v * NP + min(4 * s + g, NP - 1)) * LANES;
+            c[v][s] = C[x];
+            rs[v][s] = idet * Rb[x];
+        }
+    dx4 acc[4][TM];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int t = 0; t < TM; ++t) acc[v][t] = dx4{0.0, 0.0, 0.0, 0.0};
+
+    // volume: U and the flux cotangents at the lane's four points per tile
+#pragma unroll
+    for (int tq = 0; tq < TQ; ++tq) {
+        dx4 u[4], gr[4], gs[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) u[v] = gr[v] = gs[v] = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KP; ++s) {
+            const double a = A(L.phi + tq * KP + s), ar = A(L.dre + tq * KP + s), as = A(L.dse + tq * KP + s);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                u[v] = mfma16(a, c[v][s], u[v]);
+                gr[v] = mfma16(ar, rs[v][s], gr[v]);
+                gs[v] = mfma16(as, rs[v][s], gs[v]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double U[4], Xv[4], Yv[4], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                U[v] = u[v][r];
+                Xv[v] = a00 * gr[v][r] + a10 * gs[v][r];
+                Yv[v] = a01 * gr[v][r] + a11 * gs[v][r];
+            }
+            flux_vjp(gm1, U, Xv, Yv, Ub);
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) {
+                const double a = A(L.phl + (tm * TQ + tq) * 4 + r);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v][tm] = mfma16(a, Ub[v], acc[v][tm]);
+            }
+        }
+    }
+
+    // the neighbours' traces of state and scaled cotangent, the points
+    // facing each side kept in LDS (reversed)
+    const int sides = sside[state_off(e, 1)];
+    const int* const nb = snb + state_off(e, 3);
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        const int ne_ = nb[q * LANES];
+        const int nbase = state_off(ne_, 4 * NP);
+        const double idn = geo[state_off(ne_, 6) + 4 * LANES];
+        const int qn = (sides >> (2 * q)) & 3;
+#pragma unroll
+        for (int v0 = 0; v0 < 4; v0 += NVH) {
+            double cn[NVH][KP], rn[NVH][KP];
+#pragma unroll
+            for (int v = 0; v < NVH; ++v)
+#pragma unroll
+                for (int s = 0; s < KP; ++s) {
+                    const int x = nbase + ((v0 + v) * NP + min(4 * s + g, NP - 1)) * LANES;
+                    cn[v][s] = C[x];
+                    rn[v][s] = idn * Rb[x];
+                }
+#pragma unroll
+            for (int ts = 0; ts < TS; ++ts) {
+                dx4 tc[NVH], tr[NVH];
+#pragma unroll
+                for (int v = 0; v < NVH; ++v) tc[v] = tr[v] = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KP; ++s) {
+                    const double a = A(L.pe + ts * KP + s);
+#pragma unroll
+                    for (int v = 0; v < NVH; ++v) {
+                        tc[v] = mfma16(a, cn[v][s], tc[v]);
+                        tr[v] = mfma16(a, rn[v][s], tr[v]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * ts + row(r) - qn * NE;  // point of the neighbour's side qn
+                    if (k >= 0 && k < NE) {
+#pragma unroll
+                        for (int v = 0; v < NVH; ++v) {
+                            xc[w][q][v0 + v][NE - 1 - k][j] = tc[v][r];
+                            xr[w][q][v0 + v][NE - 1 - k][j] = tr[v][r];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+
+    // own traces, the numerical flux's cotangent and its state cotangent at
+    // each side point, lifted with the side table
+    const int bcv = BC ? sbc[state_off(e, 1)] : 0;
+    double G[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) G[v] = BC ? bcs[v] : 0.0;
+#pragma unroll
+    for (int ts = 0; ts < TS; ++ts) {
+        dx4 ul[4], rl[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ul[v] = rl[v] = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KP; ++s) {
+            const double a = A(L.pe + ts * KP + s);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                ul[v] = mfma16(a, c[v][s], ul[v]);
+                rl[v] = mfma16(a, rs[v][s], rl[v]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int sp = 16 * ts + row(r);
+            const int q = min(sp / NE, 2);
+            const bool pad = sp >= NS;
+            const int k = min(sp - q * NE, NE - 1);
+            const int go = state_off(e, 9) + 3 * q * LANES;
+            const double nx = sgeo[go], ny = sgeo[go + LANES], hl = sgeo[go + 2 * LANES];
+            const int bc = BC ? (bcv >> (4 * q)) & 15 : 0;
+            const double wk = -hl * tab[O::GW + k];
+            double UL[4], UR[4], Fb[4], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                UL[v] = ul[v][r];
+                UR[v] = pad ? UL[v] : xc[w][q][v][k][j];
+                const double rr = (pad || bc) ? 0.0 : xr[w][q][v][k][j];
+                Fb[v] = wk * (rl[v][r] - rr);
+            }
+            if constexpr (BC) {
+                ghost_state<double>(bc, UL, nx, ny, G, UR);
+                llf_vjp_side(bc, gamma, gm1, UL, UR, nx, ny, Fb, Ub);
+            } else {
+                llf_vjp_left(gamma, gm1, UL, UR, nx, ny, Fb, Ub);
+            }
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) {
+                const double a = A(L.pel + (tm * TS + ts) * 4 + r);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v][tm] = mfma16(a, Ub[v], acc[v][tm]);
+            }
+        }
+    }
+
+    const double h = MODE == 0 ? 1.0 : (dt_dev ? dt_dev[0] : dt);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int s = 0; s < KP; ++s) {
+            const int jm = 4 * s + g;
+            if (jm < NP) {
+                const int x = base + (v * NP + jm) * LANES;
+                const double cb = acc[v][s / 4][s % 4];
+                double val;
+                if (!real) {
+                    val = 0.0;
+                } else if constexpr (MODE == 0) {
+                    val = cb;
+                } else if constexpr (MODE == 1) {
+                    val = (2.0 / 3.0) * Rb[x] + (2.0 / 3.0) * (h * cb);
+                } else if constexpr (MODE == 2) {
+                    val = 0.25 * Rb[x] + 0.25 * (h * cb);
+                } else {
+                    val = (1.0 / 3.0) * X[x] + 0.75 * Y[x] + Rb[x] + h * cb;
+                }
+                out[x] = val;
+            }
+        }
+}
+
 // U_h at the volume points, user order [N][NQ][4] (a1 on its own, for
 // functionals of the solution)
 template <int P>
@@ -2443,6 +2668,21 @@ struct Launch {
     static void stage_vjp_t(const MeshDev& m, int mode, const double* C, const double* Rb, const double* X,
                             const double* Y, double* out, double dt, const double* dt_dev, hipStream_t s)
     {
+        if (m.mx_vjp) {
+            dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
+#define DG_VJPMX(MODE)                                                                                          \
+    k_stage_vjp_mx<P, MODE, BC><<<g4, BLOCK, 0, s>>>(m.n, m.npad, C, Rb, X, Y, out, m.geo, m.side_nb, m.side_q, \
+                                                     m.side_g, m.tabmx, m.tab, m.gamma, dt, dt_dev, m.side_bc,  \
+                                                     m.bc_state)
+            switch (mode) {
+            case 0: DG_VJPMX(0); break;
+            case 1: DG_VJPMX(1); break;
+            case 2: DG_VJPMX(2); break;
+            default: DG_VJPMX(3); break;
+            }
+#undef DG_VJPMX
+            return;
+        }
         if (P >= 4 || m.vjp_lanes4) {
             dim3 g4((((m.npad + 63) / 64) + 7) / 8 * 8);
 #define DG_VJP4(MODE)                                                                                                  \

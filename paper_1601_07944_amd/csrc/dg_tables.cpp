@@ -367,6 +367,19 @@ std::vector<double> build_mx_tables(int p, const std::vector<double>& t, const T
                     const int j = mode(tm, i), sp = 16 * ts + row(k, s);
                     const bool in = j < x.np && sp < x.ns;
                     put(x.le + (tm * x.ts + ts) * 4 + s, lane, in ? t[L.gw + sp % x.ne] * t[L.phs + sp * x.np + j] : 0.0);
+                    put(x.pel + (tm * x.ts + ts) * 4 + s, lane, in ? t[L.phs + sp * x.np + j] : 0.0);
+                }
+        for (int tq = 0; tq < x.tq; ++tq)
+            for (int s = 0; s < x.kp; ++s) {
+                const int pt = std::min(16 * tq + i, x.nq - 1), j = 4 * s + k;
+                put(x.dre + tq * x.kp + s, lane, j < x.np ? t[L.drw + pt * x.np + j] : 0.0);
+                put(x.dse + tq * x.kp + s, lane, j < x.np ? t[L.dsw + pt * x.np + j] : 0.0);
+            }
+        for (int tm = 0; tm < x.tm; ++tm)
+            for (int tq = 0; tq < x.tq; ++tq)
+                for (int s = 0; s < 4; ++s) {
+                    const int j = mode(tm, i), pt = 16 * tq + row(k, s);
+                    put(x.phl + (tm * x.tq + tq) * 4 + s, lane, j < x.np && pt < x.nq ? t[L.phi + pt * x.np + j] : 0.0);
                 }
     }
     return o;

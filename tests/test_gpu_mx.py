@@ -210,6 +210,8 @@ def test_automatic_choice(p, auto_mx):
     four.set_lanes(4)
     k = 16 if auto_mx else 4
     assert auto.kernel_choice() == (k, k)
+    assert auto.adjoint_kernel() == (16 if p in (3, 4) else 4)
+    assert forced.adjoint_kernel() == 16 and vec.adjoint_kernel() == 4
     assert forced.kernel_choice() == (16, 16) and vec.kernel_choice() == (4, 4) and four.kernel_choice() == (4, 4)
     Cg = auto.pack(dev(C))
     Ra, Rm, Rv, R4 = auto.rhs(Cg), forced.rhs(Cg), vec.rhs(Cg), four.rhs(Cg)
@@ -290,3 +292,55 @@ def test_mixed_boundaries_and_fused_step_length(kind, p):
         dm.rk_step(Cs, dt_dev=dt_dev, prec=1)
     torch.cuda.synchronize()
     assert torch.equal(Ca, Cs)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("mname", ["delaunay517", "square23_j0.2"])
+def test_adjoint_rhs_vjp(mname, p):
+    # the adjoint on the matrix cores (forced on): the VJP of the right-hand
+    # side against the oracle's hand-written adjoint, 1e-11
+    mesh = MESHES[mname]()
+    orc = O.Oracle(mesh, p)
+    C = W.random_state(mesh.n_elem, orc.np, seed=30 + p)
+    Rb = np.random.default_rng(30 + p).normal(size=C.shape)
+    dm = mx_mesh(mesh, p)
+    case(f"dg_rhs_vjp matrix cores p={p} {mname}")
+    got = dm.unpack(dm.rhs_vjp(dm.pack(dev(C)), dm.pack(dev(Rb)))).cpu().numpy()
+    assert rel_l2(got, orc.rhs_vjp(C, Rb)) <= TOL
+
+
+@pytest.mark.parametrize("p", [1, 3, 4])
+def test_adjoint_rk_step_vjp(p):
+    # the adjoint of one SSP-RK3 step (stage modes 1..3) with stored and with
+    # recomputed stage states
+    mesh = W.delaunay_mesh(700, 9)
+    orc = O.Oracle(mesh, p)
+    C = orc.project(W.density_jump)
+    dt, _ = orc.max_dt(C, 0.3 / (2 * p + 1))
+    ub = np.random.default_rng(p).normal(size=C.shape)
+    dm = mx_mesh(mesh, p)
+    Cg, ubg = dm.pack(dev(C)), dm.pack(dev(ub))
+    ref = orc.rk3_step_vjp(C, dt, ub)
+    case(f"dg_rk_step_vjp matrix cores p={p}")
+    got = dm.unpack(dm.rk_step_vjp(Cg, ubg, dt)).cpu().numpy()
+    assert rel_l2(got, ref) <= TOL
+    u1, u2 = dm.empty_state(), dm.empty_state()
+    Cw = Cg.clone()
+    dm.rk_step_stages(Cw, u1, u2, dt)
+    got = dm.unpack(dm.rk_step_vjp(Cg, ubg, dt, u1=u1, u2=u2)).cpu().numpy()
+    assert rel_l2(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+@pytest.mark.parametrize("kind", sorted(BOXES))
+def test_adjoint_through_ghost_states(kind, p):
+    mesh = W.box_mesh(14, 12, 1.0, 1.0, 0.2, 4, bc=BOXES[kind])
+    orc = O.Oracle(mesh, p)
+    orc.set_bc_state(U_FAR)
+    dm = mx_mesh(mesh, p)
+    dm.set_boundary_state(U_FAR)
+    C = orc.project(flow) + 0.01 * W.random_state(mesh.n_elem, orc.np, seed=p)
+    Rb = np.random.default_rng(40 + p).normal(size=C.shape)
+    case(f"dg_rhs_vjp matrix cores box={kind} p={p}")
+    got = dm.unpack(dm.rhs_vjp(dm.pack(dev(C)), dm.pack(dev(Rb)))).cpu().numpy()
+    assert rel_l2(got, orc.rhs_vjp(C, Rb)) <= TOL

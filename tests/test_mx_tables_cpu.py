@@ -67,6 +67,25 @@ def expected_blocks(p, fp64):
                     m, sp = mode(fp64, b, i), 16 * a + row(fp64, k, s)
                     return gw[sp] * ps[sp, m] if (m < np_ and sp < ns) else 0.0
                 out.append(block(f))
+    # the adjoint's transposed contractions
+    for tab in (drw, dsw):
+        for a in range(tq):
+            for s in range(kp):
+                out.append(block(lambda i, k: tab[min(16 * a + i, nq - 1), 4 * s + k] if 4 * s + k < np_ else 0.0))
+    for b in range(tm):
+        for a in range(tq):
+            for s in range(4):
+                def f(i, k):
+                    m, pt = mode(fp64, b, i), 16 * a + row(fp64, k, s)
+                    return phi[pt, m] if (m < np_ and pt < nq) else 0.0
+                out.append(block(f))
+    for b in range(tm):
+        for a in range(ts):
+            for s in range(4):
+                def f(i, k):
+                    m, sp = mode(fp64, b, i), 16 * a + row(fp64, k, s)
+                    return ps[sp, m] if (m < np_ and sp < ns) else 0.0
+                out.append(block(f))
     return np.array(out)
 
 
