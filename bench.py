@@ -552,6 +552,18 @@ def counter_pass(args):
             torch.cuda.synchronize()
             log(f"counter pass: p={p} {name} {args.steps} steps")
             del C
+        if args.counter_adjoint:
+            # --steps step adjoints (stage states stored, fixed dt)
+            _, dt = dm.max_dt(C0, 0.3 / (2 * p + 1))
+            u1, u2 = dm.empty_state(), dm.empty_state()
+            Cs = C0.clone()
+            dm.rk_step_stages(Cs, u1, u2, dt)
+            g = torch.ones_like(C0)
+            for _ in range(args.steps):
+                g = dm.rk_step_vjp(C0, g, dt, u1=u1, u2=u2)
+            torch.cuda.synchronize()
+            log(f"counter pass: p={p} {args.steps} step adjoints")
+            del Cs, u1, u2, g
         dm.close()
         del C0, dm
         torch.cuda.empty_cache()
@@ -588,6 +600,8 @@ def main():
     ap.add_argument("--counter-pass", action="store_true",
                     help="for rocprofv3 --pmc runs: --steps steps, then a 256 MiB copy; prints nothing else")
     ap.add_argument("--counter-prec", default="fp64", help="fp64, mixed or both (comma-separated)")
+    ap.add_argument("--counter-adjoint", action="store_true",
+                    help="counter pass: also --steps step adjoints (SSP-RK3, stage states stored)")
     ap.add_argument("--counter-workload", choices=["target", "cache_resident"], default="target")
     ap.add_argument("--p", default="3", help="orders of the counter pass (comma-separated)")
     args = ap.parse_args()

@@ -2229,16 +2229,22 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp_mx(int n, int npad, const d
     const double* tl = tmx + lane;
     auto A = [&](int b) { return tl[b * WAVE]; };
 
-    // own state and right-hand-side cotangent scaled by 1/det J, modes 4s+g
-    double c[4][KP], rs[4][KP];
+    // own state and right-hand-side cotangent, modes 4s+g; up to p = 3 the
+    // cotangent is kept as read, for the stage combination, and scaled by
+    // 1/det J where it enters a contraction; from p = 4 on it is kept
+    // scaled and read again for the combination (the registers it would
+    // hold cost more there)
+    constexpr bool KEEP = P <= 3;
+    double c[4][KP], rv[4][KP];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int s = 0; s < KP; ++s) {
             const int x = base + (v * NP + min(4 * s + g, NP - 1)) * LANES;
             c[v][s] = C[x];
-            rs[v][s] = idet * Rb[x];
+            rv[v][s] = KEEP ? Rb[x] : idet * Rb[x];
         }
+    auto rs = [&](int v, int s) { return KEEP ? idet * rv[v][s] : rv[v][s]; };
     dx4 acc[4][TM];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -2257,8 +2263,8 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp_mx(int n, int npad, const d
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 u[v] = mfma16(a, c[v][s], u[v]);
-                gr[v] = mfma16(ar, rs[v][s], gr[v]);
-                gs[v] = mfma16(as, rs[v][s], gs[v]);
+                gr[v] = mfma16(ar, rs(v, s), gr[v]);
+                gs[v] = mfma16(as, rs(v, s), gs[v]);
             }
         }
 #pragma unroll
@@ -2331,6 +2337,19 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp_mx(int n, int npad, const d
     }
     wave_sync();
 
+    // stage 3 combines two more cotangents: requested here, used at the end
+    double xv[MODE == 3 ? 4 : 1][MODE == 3 ? KP : 1], yv[MODE == 3 ? 4 : 1][MODE == 3 ? KP : 1];
+    if constexpr (MODE == 3) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int s = 0; s < KP; ++s) {
+                const int x = base + (v * NP + min(4 * s + g, NP - 1)) * LANES;
+                xv[v][s] = __builtin_nontemporal_load(&X[x]);
+                yv[v][s] = __builtin_nontemporal_load(&Y[x]);
+            }
+    }
+
     // own traces, the numerical flux's cotangent and its state cotangent at
     // each side point, lifted with the side table
     const int bcv = BC ? sbc[state_off(e, 1)] : 0;
@@ -2348,7 +2367,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp_mx(int n, int npad, const d
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 ul[v] = mfma16(a, c[v][s], ul[v]);
-                rl[v] = mfma16(a, rs[v][s], rl[v]);
+                rl[v] = mfma16(a, rs(v, s), rl[v]);
             }
         }
 #pragma unroll
@@ -2393,19 +2412,20 @@ __global__ __launch_bounds__(BLOCK) void k_stage_vjp_mx(int n, int npad, const d
             if (jm < NP) {
                 const int x = base + (v * NP + jm) * LANES;
                 const double cb = acc[v][s / 4][s % 4];
+                const double rb = KEEP ? rv[v][s] : Rb[x];
                 double val;
                 if (!real) {
                     val = 0.0;
                 } else if constexpr (MODE == 0) {
                     val = cb;
                 } else if constexpr (MODE == 1) {
-                    val = (2.0 / 3.0) * Rb[x] + (2.0 / 3.0) * (h * cb);
+                    val = (2.0 / 3.0) * rb + (2.0 / 3.0) * (h * cb);
                 } else if constexpr (MODE == 2) {
-                    val = 0.25 * Rb[x] + 0.25 * (h * cb);
+                    val = 0.25 * rb + 0.25 * (h * cb);
                 } else {
-                    val = (1.0 / 3.0) * X[x] + 0.75 * Y[x] + Rb[x] + h * cb;
+                    val = (1.0 / 3.0) * xv[v][s] + 0.75 * yv[v][s] + rb + h * cb;
                 }
-                out[x] = val;
+                __builtin_nontemporal_store(val, &out[x]);
             }
         }
 }
