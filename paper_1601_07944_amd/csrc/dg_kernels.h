@@ -1542,9 +1542,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
     }
     wave_sync();
 
-    // own traces, the numerical flux eq. (llf) at each side point, scaled
-    // by minus the half side length (the Gauss weights are in the table),
-    // and the lift
+    // own traces, the numerical flux of eq. (surface) (local Lax-Friedrichs)
+    // at each side point, scaled by minus the half side length (the Gauss
+    // weights are in the table), and the lift
     const int bcv = BC ? sbc[state_off(e, 1)] : 0;
     T G[4];
 #pragma unroll
