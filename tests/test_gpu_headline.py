@@ -9,7 +9,8 @@ kernel): one dg_rhs, and one dg_advance step in the launch configuration the
 benchmark times (step length from the per-block minima, fused into the stage
 kernels), FP64 within 1e-11 relative L2 of the oracle and the step length
 within 1e-14; the mixed form's step within 1e-5 (its stated bound for
-states); and the increment of one step ten times the CFL step.
+states); and the increment of one step ten times the CFL step.  At p = 3
+also the adjoint of the right-hand side (the matrix-core adjoint kernel).
 
 The mixed form's right-hand side is held to 1e-4 here, not to the 3e-5 of
 the 1,800-element meshes of the mixed-precision tests: its FP32 traces and
@@ -111,4 +112,28 @@ def test_headline_rhs_and_fused_step(mesh, p):
               f"|increment| / |state| {np.linalg.norm(inc) / np.linalg.norm(C0):.1e}", file=sys.stderr, flush=True)
         assert err <= tol
         del A, got
+    dm.close()
+
+
+def test_headline_adjoint_p3(mesh):
+    # the adjoint the benchmark times at this point (the matrix-core kernel at
+    # p=3): dg_rhs_vjp of the whole state against the oracle's hand-written
+    # adjoint (serial, about ten seconds here), 1e-11
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+
+    p = 3
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.density_jump)
+    Rb = np.random.default_rng(11).normal(size=C0.shape)
+    dm = B.DGMesh.from_mesh(mesh, p)
+    assert dm.adjoint_kernel() == 16
+    case(f"headline dg_rhs_vjp p={p} N={mesh.n_elem}")
+    got = dm.unpack(dm.rhs_vjp(dm.pack(torch.from_numpy(C0).cuda()), dm.pack(torch.from_numpy(Rb).cuda())))
+    got = got.cpu().numpy()
+    ref = orc.rhs_vjp(C0, Rb)
+    err = rel_l2(got, ref)
+    print(f"headline p={p} dg_rhs_vjp rel L2 {err:.2e}", file=sys.stderr, flush=True)
+    assert err <= 1e-11
     dm.close()

@@ -295,7 +295,7 @@ def test_mixed_boundaries_and_fused_step_length(kind, p):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
-@pytest.mark.parametrize("mname", ["delaunay517", "square23_j0.2"])
+@pytest.mark.parametrize("mname", sorted(MESHES))
 def test_adjoint_rhs_vjp(mname, p):
     # the adjoint on the matrix cores (forced on): the VJP of the right-hand
     # side against the oracle's hand-written adjoint, 1e-11
