@@ -395,8 +395,9 @@ int dg_set_lanes_per_element(dg_mesh m, int lanes);
  * uses that kernel for every stage, whatever the lane count; 0 the
  * vector-ALU kernels chosen by dg_set_lanes_per_element; -1 (the default)
  * automatic: the matrix cores at p = 4 at every size and at p = 3 and 5 up
- * to DG_LANES4_MAX_ELEMENTS elements, as long as the lane count is automatic
- * too (an explicit 1 or 4 keeps the vector-ALU kernels).  The adjoint
+ * to DG_LANES4_MAX_ELEMENTS elements (DG_MIXED: at p = 5 at every size), as
+ * long as the lane count is automatic too (an explicit 1 or 4 keeps the
+ * vector-ALU kernels).  The adjoint
  * (dg_rhs_vjp, dg_rk_step_vjp) has a matrix-core kernel of the same layout:
  * used with on = 1, and automatically at p = 3 and 4 when the lane count is
  * automatic.  Same result to rounding.  Returns DG_EINVAL for other values
@@ -457,7 +458,11 @@ int64_t dg_reference_tables(int p, double* out, int64_t cap);
  *   [tm][t][s'] (TM x TQ x 4): phi of mode mode(tm, i) at volume point
  *     16t+row(k, s') (zero past N_q);
  *   [tm][ts][s'] (TM x TS x 4): phi of mode mode(tm, i) at side point
- *     16ts+row(k, s') (zero past the last side point).
+ *     16ts+row(k, s') (zero past the last side point);
+ * and where 3(p+1) exceeds 16 by NT <= 4 (p = 5: NT = 2), for the forward
+ * kernel's per-lane evaluation of side points 16.. (lane 16g+j, any j):
+ *   [pt][s] (NT x KP): phi_{4s+g} at side point 16+pt;
+ *   [pt][s] (NT x KP): Gauss weight times phi_{4s+g} at side point 16+pt.
  * Returns the number of doubles written (> 0), or a negative dg_status. */
 int64_t dg_matrix_core_tables(int p, int fp64, double* out, int64_t cap);
 

@@ -57,7 +57,10 @@ namespace {
 //   matrix cores: at p = 4 at every size, at p = 3 and 5 up to
 //     DG_LANES4_MAX_ELEMENTS elements (beyond that the one-lane kernel at
 //     p = 3 and the four-lane kernel at p = 5 are faster), never at p <= 2
-//     (the 16 x 4 products would be mostly padding); the adjoint on the
+//     (the 16 x 4 products would be mostly padding); the mixed form also
+//     at p = 5 at every size (its FP32 kernel evaluates the two side points
+//     past the first tile per lane, which the FP64 one cannot afford in
+//     registers: 4.08 against 4.32 ms per stage at 4M triangles); the adjoint on the
 //     matrix cores at p = 3, 4 at every size (8-13% faster than four lanes
 //     at 4M triangles; slower at p = 2, and at p = 5 it holds too many
 //     registers).
@@ -71,7 +74,7 @@ void apply_kernel_choice(dg_mesh m)
     d.vjp_lanes4 = m->lanes_req == 4 || (m->lanes_req == 0 && (d.lanes4 || d.p >= 3));
     const bool mx_auto = m->lanes_req == 0 && (d.p == 4 || ((d.p == 3 || d.p == 5) && small));
     d.mx = m->mx_req == 1 || (m->mx_req == -1 && mx_auto);
-    d.mx32 = d.mx;
+    d.mx32 = m->mx_req == 1 || (m->mx_req == -1 && m->lanes_req == 0 && (mx_auto || d.p == 5));
     d.mx_vjp = m->mx_req == 1 || (m->mx_req == -1 && m->lanes_req == 0 && (d.p == 3 || d.p == 4));
 }
 

@@ -56,6 +56,11 @@ constexpr int WAVE = 64;
 //                   16t+mx_row(k, s') (zero past the last point)
 //   PEL [tm][ts][s'] phi of mode mx_mode(tm, i) at side point
 //                   16ts+mx_row(k, s') (zero past the last side point)
+// and, where the side points overrun one tile by a few (p = 5: 18 points,
+// NT = 2), for the forward kernel's per-lane evaluation of those points
+// (lane 16g+j holds, whatever j):
+//   TPE [pt][s]     phi_{4s+g} at side point 16+pt
+//   TLE [pt][s]     Gauss weight times phi_{4s+g} at side point 16+pt
 // Entries of modes >= N_p are zero.
 // Result rows: the FP64 product puts row 4r+g in register r of lane group
 // g, the FP32 product row 4g+r; mx_mode orders the mode rows so that
@@ -66,7 +71,8 @@ template <bool F64>
 constexpr int mx_mode(int tm, int i) { return F64 ? 16 * tm + i : 4 * (4 * tm + i % 4) + i / 4; }
 struct MxLayout {
     int np, nq, ne, ns, kp, tq, ts, tm;
-    int phi, dr, ds, pe, le, dre, dse, phl, pel, blocks;
+    int nt;  // side points past the first tile evaluated per lane (0: none)
+    int phi, dr, ds, pe, le, dre, dse, phl, pel, tpe, tle, blocks;
 };
 constexpr MxLayout mx_layout(int p)
 {
@@ -88,7 +94,10 @@ constexpr MxLayout mx_layout(int p)
     x.dse = x.dre + x.tq * x.kp;
     x.phl = x.dse + x.tq * x.kp;
     x.pel = x.phl + x.tm * x.tq * 4;
-    x.blocks = x.pel + x.tm * x.ts * 4;
+    x.nt = x.ns > 16 && x.ns <= 20 ? x.ns - 16 : 0;
+    x.tpe = x.pel + x.tm * x.ts * 4;
+    x.tle = x.tpe + x.nt * x.kp;
+    x.blocks = x.tle + x.nt * x.kp;
     return x;
 }
 

@@ -1403,6 +1403,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
     constexpr bool F64 = sizeof(T) == sizeof(double);
     constexpr MxLayout X = mx_layout(P);
     constexpr int NP = X.np, NE = X.ne, NS = X.ns, KP = X.kp, TQ = X.tq, TS = X.ts, TM = X.tm;
+    // side points past the first tile (p = 5: 2 of 18) are evaluated per
+    // lane, a dot product over the lane's modes added up over the column's
+    // four lanes, instead of a second tile of products that is mostly
+    // padding; in the mixed form only (the FP64 kernel would need more than
+    // 256 registers for it at p = 5 and lose its second wavefront per SIMD)
+    constexpr int NTL = F64 ? 0 : X.nt, TSP = NTL ? 1 : TS;
     constexpr int NW = BLOCK / WAVE;
     constexpr int NVH = 2;  // neighbour variables gathered together (half the registers of four)
     __shared__ T xs[NW][3][4][NE][LANES];  // neighbour traces facing each side, per wavefront
@@ -1502,7 +1508,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
         const int q = t / (4 / NVH), v0 = (t % (4 / NVH)) * NVH;
         const int qn = (sides >> (2 * q)) & 3;
 #pragma unroll
-        for (int ts = 0; ts < TS; ++ts) {
+        for (int pt = 0; pt < NTL; ++pt) {
+            const int k = 16 + pt - qn * NE;  // point of the neighbour's side qn
+#pragma unroll
+            for (int v = 0; v < NVH; ++v) {
+                T d = T(0);
+#pragma unroll
+                for (int s = 0; s < KP; ++s) d = fma(A(X.tpe + pt * KP + s), cn[v][s], d);
+                d += __shfl_xor(d, 16);
+                d += __shfl_xor(d, 32);
+                if (g == 0 && k >= 0 && k < NE) xs[w][q][v0 + v][NE - 1 - k][j] = d;
+            }
+        }
+#pragma unroll
+        for (int ts = 0; ts < TSP; ++ts) {
             V tn[NVH];
 #pragma unroll
             for (int v = 0; v < NVH; ++v) tn[v] = V{0, 0, 0, 0};
@@ -1551,7 +1570,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
     for (int v = 0; v < 4; ++v) G[v] = BC ? T(bcs[v]) : T(0);
     double acc0[4] = {0.0, 0.0, 0.0, 0.0};  // mixed form: the mean mode in FP64
 #pragma unroll
-    for (int ts = 0; ts < TS; ++ts) {
+    for (int ts = 0; ts < TSP; ++ts) {
         V ul[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) ul[v] = V{0, 0, 0, 0};
@@ -1590,6 +1609,56 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
                 for (int v = 0; v < 4; ++v) acc[v][tm] = mfma16(a, T(-hl) * F[v], acc[v][tm]);
             }
         }
+    }
+    if constexpr (NTL > 0) {
+        // the side points past the first tile: lane group g < NTL takes point
+        // 16+g (its traces summed over the column's lanes), and every lane
+        // lifts all of them onto its own modes
+        T ut[NTL][4];
+#pragma unroll
+        for (int pt = 0; pt < NTL; ++pt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                T d = T(0);
+#pragma unroll
+                for (int s = 0; s < KP; ++s) d = fma(A(X.tpe + pt * KP + s), T(c[v][s]), d);
+                d += __shfl_xor(d, 16);
+                d += __shfl_xor(d, 32);
+                ut[pt][v] = d;
+            }
+        const bool pad = g >= NTL;
+        const int sp = 16 + min(g, NTL - 1);
+        const int q = min(sp / NE, 2);
+        const int go = state_off(e, 9) + 3 * q * LANES;
+        const T nx = T(sgeo[go]), ny = T(sgeo[go + LANES]);
+        const double hl = sgeo[go + 2 * LANES];
+        const int k = min(sp - q * NE, NE - 1);
+        T UL[4], UR[4], F[4], wf[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            T u = ut[0][v];
+#pragma unroll
+            for (int pt = 1; pt < NTL; ++pt) u = g == pt ? ut[pt][v] : u;
+            UL[v] = u;
+            UR[v] = pad ? UL[v] : xs[w][q][v][k][j];
+        }
+        if constexpr (BC) ghost_state<T>((bcv >> (4 * q)) & 15, UL, nx, ny, G, UR);
+        llf<T>(gam, gm1, UL, UR, nx, ny, F);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wf[v] = pad ? T(0) : T(-hl) * F[v];
+        if constexpr (!F64) {
+            const double w0 = pad ? 0.0 : -hl * tab64[O::GW + k] * tab64[O::PHS + (q * NE + k) * NP];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc0[v] = fma(w0, double(F[v]), acc0[v]);
+        }
+#pragma unroll
+        for (int pt = 0; pt < NTL; ++pt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const T f = __shfl(wf[v], j + 16 * pt);
+#pragma unroll
+                for (int s = 0; s < KP; ++s) acc[v][s / 4][s % 4] = fma(A(X.tle + pt * KP + s), f, acc[v][s / 4][s % 4]);
+            }
     }
     if constexpr (!F64) {
         // the column's four lanes add their terms of the mean mode

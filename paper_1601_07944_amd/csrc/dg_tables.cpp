@@ -381,6 +381,13 @@ std::vector<double> build_mx_tables(int p, const std::vector<double>& t, const T
                     const int j = mode(tm, i), pt = 16 * tq + row(k, s);
                     put(x.phl + (tm * x.tq + tq) * 4 + s, lane, j < x.np && pt < x.nq ? t[L.phi + pt * x.np + j] : 0.0);
                 }
+        // lane 16g + j: k = g here
+        for (int pt = 0; pt < x.nt; ++pt)
+            for (int s = 0; s < x.kp; ++s) {
+                const int sp = 16 + pt, j = 4 * s + k;
+                put(x.tpe + pt * x.kp + s, lane, j < x.np ? t[L.phs + sp * x.np + j] : 0.0);
+                put(x.tle + pt * x.kp + s, lane, j < x.np ? t[L.gw + sp % x.ne] * t[L.phs + sp * x.np + j] : 0.0);
+            }
     }
     return o;
 }

@@ -86,6 +86,13 @@ def expected_blocks(p, fp64):
                     m, sp = mode(fp64, b, i), 16 * a + row(fp64, k, s)
                     return ps[sp, m] if (m < np_ and sp < ns) else 0.0
                 out.append(block(f))
+    # side points past the first tile, evaluated per lane (lane 16g + j: mode 4s + g)
+    nt = ns - 16 if 16 < ns <= 20 else 0
+    for scale in (np.ones(ns), gw):
+        for pt in range(nt):
+            for s in range(kp):
+                sp = 16 + pt
+                out.append(block(lambda i, k: scale[sp] * ps[sp, 4 * s + k] if 4 * s + k < np_ else 0.0))
     return np.array(out)
 
 
