@@ -266,7 +266,7 @@ def test_mixed_100_steps(p):
     assert np.all(np.abs(tot - tot0) <= 1e-12 * np.abs(tot0))
 
 
-@pytest.mark.parametrize("p", [2, 4])
+@pytest.mark.parametrize("p", [2, 4, 5])
 @pytest.mark.parametrize("kind", sorted(BOXES))
 def test_mixed_boundaries_and_fused_step_length(kind, p):
     # mixed form with domain boundaries: one right-hand side within 3e-5, and
