@@ -257,6 +257,16 @@ int dg_rk_step_vjp(dg_mesh m, const double* C_dev, double dt, const double* dt_d
 int dg_rk_step_stages(dg_mesh m, double* C_dev, double dt, const double* dt_dev, double* u1_dev, double* u2_dev,
                       void* ws_dev, void* stream);
 
+/* dg_rk_step_stages with the new state written to Cnext_dev instead of over
+ * C_dev (C_dev unchanged; Cnext_dev must not overlap C_dev, u1_dev or
+ * u2_dev): a reverse sweep that recomputes a segment of steps and keeps
+ * every step's input state then needs no copies.  The last stage is the
+ * general form (1/3 C + 2/3 u2 + 2/3 dt L(u2)), so Cnext equals dg_rk_step's
+ * result to rounding, not bit for bit; u1 and u2 are bitwise those of
+ * dg_rk_step_stages. */
+int dg_rk_step_stages_to(dg_mesh m, const double* C_dev, double* Cnext_dev, double dt, const double* dt_dev,
+                         double* u1_dev, double* u2_dev, void* ws_dev, void* stream);
+
 /* U_h at the volume quadrature points, u_dev [N][n_vol_points][4] (user
  * order): the modes-to-points contraction on its own, for functionals of
  * the solution. */

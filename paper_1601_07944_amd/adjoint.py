@@ -4,8 +4,8 @@ hand-written adjoint kernels (dg_rk_step_vjp), with checkpointing.
 Forward: N steps with a fixed step length (the step length is held fixed and
 not differentiated), keeping the state every `every` steps.  Backward: for
 each segment, last to first, recompute its steps from the checkpoint while
-keeping their stage states (dg_rk_step_stages), then chain the step adjoints
-backwards.  Memory: N/every checkpoints plus 3*every states for one segment.
+keeping their input and stage states (dg_rk_step_stages_to, which writes each
+step's result to a new state), then chain the step adjoints backwards.  Memory: N/every checkpoints plus 3*every states for one segment.
 All arithmetic runs in libdgmi's kernels; torch provides memory and streams.
 """
 from __future__ import annotations
@@ -46,14 +46,18 @@ def backward_sweep(dm, ckpts, dt, nsteps, every, gout):
     for seg in range(nseg - 1, -1, -1):
         start = seg * every
         end = min(start + every, nsteps)
-        C = ckpts[seg].clone()
+        # every step's input state is kept: each recomputed step writes its
+        # result into a new state instead of over its input (no copies)
+        C = ckpts[seg]
         saved = []
         for _ in range(start, end):
             u1 = dm.empty_state()
             u2 = dm.empty_state()
-            Cn = C.clone()
-            dm.rk_step_stages(C, u1, u2, dt)
-            saved.append((Cn, u1, u2))
+            Cnext = dm.empty_state()
+            dm.rk_step_stages_to(C, Cnext, u1, u2, dt)
+            saved.append((C, u1, u2))
+            C = Cnext
+        del C
         for Cn, u1, u2 in reversed(saved):
             g = dm.rk_step_vjp(Cn, g, dt, u1=u1, u2=u2)
     return g

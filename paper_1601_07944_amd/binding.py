@@ -48,6 +48,7 @@ EXPORTS = [
     "dg_rhs_vjp",
     "dg_rk_step_vjp",
     "dg_rk_step_stages",
+    "dg_rk_step_stages_to",
     "dg_eval_points",
     "dg_quad_weights",
     "dg_set_lanes_per_element",
@@ -127,6 +128,7 @@ def load(path: str = LIB_PATH):
     lib.dg_rhs_vjp.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.dg_rk_step_vjp.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.dg_rk_step_stages.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
+    lib.dg_rk_step_stages_to.argtypes = [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
     lib.dg_eval_points.argtypes = [_vp, _vp, _vp, _vp]
     lib.dg_quad_weights.argtypes = [_vp, _vp, _vp]
     lib.dg_set_lanes_per_element.argtypes = [_vp, i32]
@@ -460,6 +462,20 @@ class DGMesh:
         _check(self._lib.dg_rk_step_stages(self._h, _ptr(C), float(dt), _ptr(dt_dev) if dt_dev is not None else None,
                                            _ptr(u1), _ptr(u2), _ptr(ws), _stream(stream)))
         return C
+
+    def rk_step_stages_to(self, C, Cnext, u1, u2, dt=0.0, dt_dev=None, ws=None, stream=None):
+        """dg_rk_step_stages with the new state written to Cnext (C unchanged)."""
+        self._state(C, "C")
+        self._state(Cnext, "Cnext")
+        self._state(u1, "u1")
+        self._state(u2, "u2")
+        if dt_dev is not None:
+            self._dt(dt_dev)
+        ws = self.workspace("step") if ws is None else self._ws_check(ws, self.info.ws_step)
+        _check(self._lib.dg_rk_step_stages_to(self._h, _ptr(C), _ptr(Cnext), float(dt),
+                                              _ptr(dt_dev) if dt_dev is not None else None, _ptr(u1), _ptr(u2),
+                                              _ptr(ws), _stream(stream)))
+        return Cnext
 
     def rk_step_vjp(self, C, ubar, dt=0.0, dt_dev=None, u1=None, u2=None, out=None, ws=None, stream=None):
         import torch

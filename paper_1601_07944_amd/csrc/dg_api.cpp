@@ -928,6 +928,29 @@ int dg_rk_step_stages(dg_mesh m, double* C, double dt, const double* dt_dev, dou
     return check_launch("dg_rk_step_stages");
 }
 
+int dg_rk_step_stages_to(dg_mesh m, const double* C, double* Cn, double dt, const double* dt_dev, double* u1,
+                         double* u2, void* ws, void* stream)
+{
+    if (!m || !C || !Cn || !u1 || !u2) return fail(DG_EINVAL, "null argument");
+    if (Cn == C || Cn == u1 || Cn == u2) return fail(DG_EINVAL, "Cnext must not overlap C, u1 or u2");
+    if (m->integrator != DG_RK_SSP3) return fail(DG_EUNSUPPORTED, "the stage states are those of SSP-RK3");
+    (void)ws;
+    hipStream_t s = (hipStream_t)stream;
+    const dgk::MeshDev& d = m->dev;
+    timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 1, false, C, nullptr, u1, dt, dt_dev, s); });
+    limit_stage(m, u1, s);
+    timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage(d, 2, false, u1, C, u2, dt, dt_dev, s); });
+    limit_stage(m, u2, s);
+    dgk::StageGen gs;
+    gs.a = 1.0 / 3.0;
+    gs.X = C;
+    gs.b = 2.0 / 3.0;
+    gs.g = 2.0 / 3.0;
+    timed(m, DG_KERNEL_STAGE, s, [&] { dgk::launch_stage_general(d, false, u2, Cn, dt, dt_dev, gs, s); });
+    limit_stage(m, Cn, s);
+    return check_launch("dg_rk_step_stages_to");
+}
+
 int dg_rk_step_vjp(dg_mesh m, const double* C, double dt, const double* dt_dev, const double* u1_in,
                    const double* u2_in, const double* ub, double* Cb, void* ws, void* stream)
 {

@@ -183,3 +183,34 @@ def test_adjoint_gradient_finite_differences_131072():
         worst = max(worst, abs(fd - ad) / abs(fd))
         print(f"direction {s}: fd {fd:.10e} adjoint {ad:.10e}", file=sys.stderr, flush=True)
     assert worst <= 1e-6, worst
+
+
+@pytest.mark.parametrize("p", [1, 3, 4])
+def test_rk_step_stages_to(p):
+    # the out-of-place stage states of the reverse sweep: u1, u2 bit for bit
+    # those of dg_rk_step_stages, the input untouched, the new state equal
+    # to dg_rk_step's to rounding (its last stage is the general form)
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+
+    mesh = W.delaunay_mesh(700, 19)
+    orc = O.Oracle(mesh, p)
+    C = orc.project(W.density_jump)
+    dt, _ = orc.max_dt(C, 0.3 / (2 * p + 1))
+    dm = gpu_mesh(mesh, p, 0)
+    Cg = dm.pack(dev(C))
+    case(f"dg_rk_step_stages_to p={p}")
+    u1, u2, Cn = dm.empty_state(), dm.empty_state(), dm.empty_state()
+    C_in = Cg.clone()
+    dm.rk_step_stages_to(C_in, Cn, u1, u2, dt)
+    v1, v2 = dm.empty_state(), dm.empty_state()
+    Cw = Cg.clone()
+    dm.rk_step_stages(Cw, v1, v2, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(C_in, Cg)
+    assert torch.equal(u1, v1) and torch.equal(u2, v2)
+    assert float(torch.linalg.norm(Cn - Cw) / torch.linalg.norm(Cw)) <= 1e-15
+    assert rel_l2(dm.unpack(Cn).cpu().numpy(), orc.rk3_step(C, dt)) <= 1e-11
+    with pytest.raises(B.DGError):
+        dm.rk_step_stages_to(C_in, C_in, u1, u2, dt)
