@@ -344,3 +344,67 @@ def test_adjoint_through_ghost_states(kind, p):
     case(f"dg_rhs_vjp matrix cores box={kind} p={p}")
     got = dm.unpack(dm.rhs_vjp(dm.pack(dev(C)), dm.pack(dev(Rb)))).cpu().numpy()
     assert rel_l2(got, orc.rhs_vjp(C, Rb)) <= TOL
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_rk2_stages(p):
+    # the paper's RK2 (general stages) through the matrix-core kernel
+    import torch
+
+    mesh = W.delaunay_mesh(500, 60 + p)
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.smooth_density)
+    dt, _ = orc.max_dt(C0, 0.3 / (2 * p + 1))
+    dm = mx_mesh(mesh, p)
+    dm.set_integrator(1)
+    Cg = dm.pack(dev(C0))
+    ref = C0
+    case(f"RK2 x5 matrix cores p={p}")
+    for _ in range(5):
+        dm.rk_step(Cg, dt)
+        ref = orc.rk_step(ref, dt, "rk2")
+    torch.cuda.synchronize()
+    assert rel_l2(dm.unpack(Cg).cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("p", [3, 5])
+def test_mixed_rk4(p):
+    # RK4 in the mixed form on the matrix cores: within the mixed bound for
+    # states (1e-5 after 20 steps)
+    import torch
+
+    mesh = W.delaunay_mesh(900, 34)
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.smooth_density)
+    dt, _ = orc.max_dt(C0, 0.3 / (2 * p + 1))
+    dm = mx_mesh(mesh, p)
+    dm.set_integrator(2)
+    Cg = dm.pack(dev(C0))
+    ref = C0
+    case(f"mixed RK4 x20 matrix cores p={p}")
+    for _ in range(20):
+        dm.rk_step(Cg, dt, prec=1)
+        ref = orc.rk_step(ref, dt, "rk4")
+    torch.cuda.synchronize()
+    assert rel_l2(dm.unpack(Cg).cpu().numpy(), ref) <= 1e-5
+
+
+def test_limited_steps():
+    # SSP-RK3 with the Barth-Jespersen limiter after every stage, the stages
+    # on the matrix cores (forced at p=1)
+    import torch
+
+    mesh = W.delaunay_mesh(800, 33)
+    orc = O.Oracle(mesh, 1)
+    C0 = orc.project(W.density_jump)
+    dt, _ = orc.max_dt(C0, 0.1)
+    dm = mx_mesh(mesh, 1)
+    dm.set_limiter(1)
+    Cg = dm.pack(dev(C0))
+    ref = C0
+    case("limited SSP-RK3 x15 matrix cores p=1")
+    for _ in range(15):
+        dm.rk_step(Cg, dt)
+        ref = orc.rk3_step(ref, dt, limit=True)
+    torch.cuda.synchronize()
+    assert rel_l2(dm.unpack(Cg).cpu().numpy(), ref) <= TOL
