@@ -52,7 +52,7 @@ def steps_both_ways(dm, C0, p, prec, nsteps):
     return A, Bst
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("lanes", [0, 1, 4])  # 0: the automatic choice (matrix cores at p = 3, 5 here)
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("p", [1, 3, 5])
 def test_noalloc_step_equals_workspace_step(p, prec, lanes):
