@@ -1384,11 +1384,11 @@ __device__ __forceinline__ fx4 mfma16(float a, float b, fx4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// at p = 4 the FP64 kernel without domain boundaries fits three wavefronts
-// per SIMD without spilling (168 registers) when asked to (the boundary
-// variants and p = 5 would spill; p <= 3 fits three by itself)
+// at p = 4 the FP64 kernel fits three wavefronts per SIMD (at most 168
+// registers, one spilled in the boundary variant of the third stage) when
+// asked to; p = 5 would spill, p <= 3 fits three by itself
 template <int P, typename T, bool BC>
-constexpr int mx_waves = P == 4 && !BC && sizeof(T) == sizeof(double) ? 3 : 1;
+constexpr int mx_waves = P == 4 && sizeof(T) == sizeof(double) ? 3 : 1;
 template <int P, int MODE, typename T, bool BC>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<P, T, BC>))) void k_stage_mx(
     int n, int npad, const double* __restrict__ C, const double* __restrict__ U0, double* __restrict__ out,
@@ -1564,10 +1564,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
     // own traces, the numerical flux of eq. (surface) (local Lax-Friedrichs)
     // at each side point, scaled by minus the half side length (the Gauss
     // weights are in the table), and the lift
+    // boundary codes of the three sides; the ghost state (and the fixed
+    // boundary state it may take) only where a lane's side is a boundary,
+    // which keeps the boundary variant within the registers of three
+    // wavefronts per SIMD at p = 4
     const int bcv = BC ? sbc[state_off(e, 1)] : 0;
-    T G[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) G[v] = BC ? T(bcs[v]) : T(0);
     double acc0[4] = {0.0, 0.0, 0.0, 0.0};  // mixed form: the mean mode in FP64
 #pragma unroll
     for (int ts = 0; ts < TSP; ++ts) {
@@ -1595,7 +1596,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
                 UL[v] = ul[v][r];
                 UR[v] = pad ? UL[v] : xs[w][q][v][k][j];
             }
-            if constexpr (BC) ghost_state<T>((bcv >> (4 * q)) & 15, UL, nx, ny, G, UR);
+            if constexpr (BC) {
+                const int code = (bcv >> (4 * q)) & 15;
+                if (code) {
+                    T G[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) G[v] = T(bcs[v]);
+                    ghost_state<T>(code, UL, nx, ny, G, UR);
+                }
+            }
             llf<T>(gam, gm1, UL, UR, nx, ny, F);
             if constexpr (!F64) {
                 const double w0 = pad ? 0.0 : -hl * tab64[O::GW + k] * tab64[O::PHS + (q * NE + k) * NP];
@@ -1642,7 +1651,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<
             UL[v] = u;
             UR[v] = pad ? UL[v] : xs[w][q][v][k][j];
         }
-        if constexpr (BC) ghost_state<T>((bcv >> (4 * q)) & 15, UL, nx, ny, G, UR);
+        if constexpr (BC) {
+            const int code = (bcv >> (4 * q)) & 15;
+            if (code) {
+                T G[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) G[v] = T(bcs[v]);
+                ghost_state<T>(code, UL, nx, ny, G, UR);
+            }
+        }
         llf<T>(gam, gm1, UL, UR, nx, ny, F);
 #pragma unroll
         for (int v = 0; v < 4; ++v) wf[v] = pad ? T(0) : T(-hl) * F[v];
