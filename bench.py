@@ -31,7 +31,9 @@ Prints ONE JSON line.  Extra objects:
   rhs_only       dg_rhs alone;
   adjoint_forward_ratio  reverse sweep (checkpoint every 20 steps, segment
                  recomputation) over 50 steps of this workload against the
-                 forward steps, with and without recomputation;
+                 forward steps, with and without recomputation, and with
+                 every step's stage states kept by the forward pass in
+                 device memory (192 GB here; skipped if they do not fit);
   orders         p = 1..5 on this mesh, FP64 and mixed, 50 steps each:
                  DOF-updates/s, stage launch time, algorithmic HBM fraction;
                  at p = 1 also the limiter's cost;
@@ -273,6 +275,39 @@ def adjoint_ratio(dm, C0, dt, nsteps, every):
     ms_vjp = tm(vjps)
     del Cs, u1s, u2s, g
     torch.cuda.empty_cache()
+    # every step's stage states kept by the forward pass itself (3 nsteps
+    # states in device memory, every = 0): the reverse sweep is then the step
+    # adjoints alone; a first pass fills the allocator's cache
+    need = 3 * nsteps * int(dm.info.state_len) * 8
+    if A.choose_every(dm, nsteps) == 0:
+        box = {}
+
+        def fwd_keep():
+            box["CN"], box["tape"] = A.forward_keep_all(dm, box.pop("C"), dt, nsteps)
+
+        def rev_keep():
+            box["g"] = A.backward_tape(dm, box.pop("tape"), dt, gN)
+
+        times = []
+        for _ in range(2):
+            box.clear()
+            box["C"] = C0.clone()
+            t_f = tm(fwd_keep)
+            t_r = tm(rev_keep)
+            times.append((t_f, t_r))
+        box.clear()
+        ms_fk, ms_rk = times[-1]
+        keep = {
+            "ratio": ms_rk / ms_fwd,
+            "forward_keeping_over_forward": ms_fk / ms_fwd,
+            "ms_forward_keeping": ms_fk,
+            "ms_reverse": ms_rk,
+            "state_bytes": need,
+        }
+    else:
+        free, _ = torch.cuda.mem_get_info()
+        keep = {"skipped": f"needs {need / 1e9:.1f} GB of device memory, {free / 1e9:.1f} GB free"}
+    torch.cuda.empty_cache()
     return {
         "ratio": ms_rev / ms_fwd,
         "ratio_without_recompute": ms_vjp / ms_fwd,
@@ -281,6 +316,7 @@ def adjoint_ratio(dm, C0, dt, nsteps, every):
         "ms_forward": ms_fwd,
         "ms_reverse": ms_rev,
         "ms_step_adjoints_only": ms_vjp,
+        "keep_all_stage_states": keep,
     }
 
 

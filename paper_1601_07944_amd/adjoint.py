@@ -6,6 +6,12 @@ not differentiated), keeping the state every `every` steps.  Backward: for
 each segment, last to first, recompute its steps from the checkpoint while
 keeping their input and stage states (dg_rk_step_stages_to, which writes each
 step's result to a new state), then chain the step adjoints backwards.  Memory: N/every checkpoints plus 3*every states for one segment.
+
+every = 0 keeps every step's input and stage states from the forward pass
+itself (3N states, e.g. 192 GB for 50 steps of the 4,000,000-triangle mesh
+at p = 3): the backward pass then runs the step adjoints alone, with no
+recomputation.  choose_every() picks that when the states fit in the free
+device memory.
 All arithmetic runs in libdgmi's kernels; torch provides memory and streams.
 """
 from __future__ import annotations
@@ -20,23 +26,71 @@ class RKSteps(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, C0, dm, dt: float, nsteps: int, every: int = 20):
+        if every < 0:
+            raise ValueError("every must be >= 0 (0: keep every step's stage states)")
+        ctx.dm = dm
+        ctx.dt = float(dt)
+        ctx.nsteps = nsteps
+        ctx.every = every
+        if every == 0:
+            C, ctx.tape = forward_keep_all(dm, C0.detach().clone(), dt, nsteps)
+            ctx.ckpts = None
+            return C
         C = C0.detach().clone()
         ckpts = []
         for n in range(nsteps):
             if n % every == 0:
                 ckpts.append(C.clone())
             dm.rk_step(C, dt)
-        ctx.dm = dm
-        ctx.dt = float(dt)
-        ctx.nsteps = nsteps
-        ctx.every = every
         ctx.ckpts = ckpts
+        ctx.tape = None
         return C
 
     @staticmethod
     def backward(ctx, gout):
-        g = backward_sweep(ctx.dm, ctx.ckpts, ctx.dt, ctx.nsteps, ctx.every, gout.contiguous())
+        if ctx.every == 0:
+            tape, ctx.tape = ctx.tape, None
+            g = backward_tape(ctx.dm, tape, ctx.dt, gout.contiguous())
+        else:
+            g = backward_sweep(ctx.dm, ctx.ckpts, ctx.dt, ctx.nsteps, ctx.every, gout.contiguous())
         return g, None, None, None, None
+
+
+def forward_keep_all(dm, C, dt, nsteps):
+    """nsteps SSP-RK3 steps from C (which becomes the first step's input and
+    must not be modified afterwards), each step's input and stage states kept:
+    returns (C_N, tape), tape[n] = (C_n, u1_n, u2_n)."""
+    tape = []
+    for _ in range(nsteps):
+        u1, u2, Cnext = dm.empty_state(), dm.empty_state(), dm.empty_state()
+        dm.rk_step_stages_to(C, Cnext, u1, u2, dt)
+        tape.append((C, u1, u2))
+        C = Cnext
+    return C, tape
+
+
+def backward_tape(dm, tape, dt, gout):
+    """Cotangent of C_0 from that of C_N over the kept states of
+    forward_keep_all, last step first; each step's states are released
+    once its adjoint has run (the list is emptied)."""
+    g = gout.clone()
+    while tape:
+        Cn, u1, u2 = tape.pop()
+        g = dm.rk_step_vjp(Cn, g, dt, u1=u1, u2=u2)
+        del Cn, u1, u2
+    return g
+
+
+def choose_every(dm, nsteps, every=20, margin=1.10):
+    """0 (keep every step's stage states, no recomputation) if the 3 nsteps
+    states, times margin, fit in the device's free memory (the caching
+    allocator's unused blocks included), else every."""
+    import torch
+
+    free, _ = torch.cuda.mem_get_info(dm.device)
+    free += torch.cuda.memory_reserved(dm.device) - torch.cuda.memory_allocated(dm.device)
+    need = 3 * nsteps * dm.info.state_len * 8
+    return 0 if need * margin <= free else every
 
 
 def backward_sweep(dm, ckpts, dt, nsteps, every, gout):
@@ -64,7 +118,10 @@ def backward_sweep(dm, ckpts, dt, nsteps, every, gout):
 
 
 def run_steps(C0, dm, dt, nsteps, every=20):
-    """Differentiable wrapper: returns C_N."""
+    """Differentiable wrapper: returns C_N (every: the checkpoint interval,
+    0 to keep every step's stage states, None for choose_every's pick)."""
+    if every is None:
+        every = choose_every(dm, nsteps)
     return RKSteps.apply(C0, dm, dt, nsteps, every)
 
 

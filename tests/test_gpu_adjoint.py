@@ -214,3 +214,46 @@ def test_rk_step_stages_to(p):
     assert rel_l2(dm.unpack(Cn).cpu().numpy(), orc.rk3_step(C, dt)) <= 1e-11
     with pytest.raises(B.DGError):
         dm.rk_step_stages_to(C_in, C_in, u1, u2, dt)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_keep_all_adjoint_equals_checkpointed(p):
+    # every = 0 (the forward pass keeps every step's stage states with
+    # dg_rk_step_stages_to, no recomputation) against the checkpointed sweep:
+    # with one segment (every >= nsteps) the sweep recomputes the same
+    # out-of-place steps from C0, so the gradients agree bit for bit; with
+    # checkpoints every 5 steps, taken from dg_rk_step (whose last stage
+    # rounds differently), within 1e-12; the same cotangent of C_N seeds all
+    # three; C_N within 1e-14; choose_every picks 0 when the states fit
+    import torch
+
+    from paper_1601_07944_amd import adjoint as A
+
+    mesh = W.delaunay_mesh(900, 60 + p)
+    dm = gpu_mesh(mesh, p)
+    xy = dm.quad_points().cpu().numpy()
+    C0 = dm.project(dev(W.smooth_density(xy[..., 0], xy[..., 1])))
+    _, dt = dm.max_dt(C0, 0.3 / (2 * p + 1))
+    nsteps = 23
+    case(f"keep-all adjoint vs checkpointed, p={p}, {mesh.n_elem} elements, {nsteps} steps")
+    grads, outs, gN = {}, {}, None
+    for every in (nsteps, 5, 0):
+        x = C0.clone().requires_grad_(True)
+        CN = A.run_steps(x, dm, dt, nsteps, every)
+        if gN is None:  # one cotangent of C_N for all three sweeps
+            _, gN = A.pressure_disk_objective(dm, CN.detach())
+        CN.backward(gN)
+        grads[every] = x.grad.detach().clone()
+        outs[every] = CN.detach().clone()
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+    assert rel(outs[0], outs[nsteps]) <= 1e-14
+    assert torch.equal(grads[0], grads[nsteps])
+    assert rel(grads[0], grads[5]) <= 1e-12
+    assert A.choose_every(dm, nsteps) == 0
+    assert A.choose_every(dm, 10**9) == 20
+    with pytest.raises(ValueError):
+        A.run_steps(C0.clone().requires_grad_(True), dm, dt, 3, -1)
