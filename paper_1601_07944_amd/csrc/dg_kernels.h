@@ -1384,13 +1384,14 @@ __device__ __forceinline__ fx4 mfma16(float a, float b, fx4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// at p = 4 the FP64 kernel fits three wavefronts per SIMD (at most 168
-// registers, one spilled in the boundary variant of the third stage) when
-// asked to; p = 5 would spill, p <= 3 fits three by itself
-template <int P, typename T, bool BC>
-constexpr int mx_waves = P == 4 && sizeof(T) == sizeof(double) ? 3 : 1;
+// at p = 4 the FP64 kernel fits three wavefronts per SIMD without spilling
+// (at most 168 registers) when asked to, except the boundary variant of the
+// third stage (fused step-length partials), which would spill and keeps two;
+// p = 5 would spill, p <= 3 fits three by itself
 template <int P, int MODE, typename T, bool BC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<P, T, BC>))) void k_stage_mx(
+constexpr int mx_waves = P == 4 && sizeof(T) == sizeof(double) && !(BC && MODE == 3) ? 3 : 1;
+template <int P, int MODE, typename T, bool BC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mx_waves<P, MODE, T, BC>))) void k_stage_mx(
     int n, int npad, const double* __restrict__ C, const double* __restrict__ U0, double* __restrict__ out,
     const double* __restrict__ geo, const int* __restrict__ snb, const int* __restrict__ sside,
     const double* __restrict__ sgeo, const T* __restrict__ tmx, const double* __restrict__ tab64, double gamma,
