@@ -12,6 +12,9 @@ within 1e-14; the mixed form's step within 1e-5 (its stated bound for
 states); and the increment of one step ten times the CFL step.  At p = 3
 also the adjoint of the right-hand side (the matrix-core adjoint kernel).
 
+Also a channel of the same size class with all three boundary kinds
+(2,000,000 triangles, p = 4: the matrix-core kernel's boundary variants).
+
 The mixed form's right-hand side is held to 1e-4 here, not to the 3e-5 of
 the 1,800-element meshes of the mixed-precision tests: its FP32 traces and
 fluxes are rounded relative to their own size (about 1), while the
@@ -136,4 +139,63 @@ def test_headline_adjoint_p3(mesh):
     err = rel_l2(got, ref)
     print(f"headline p={p} dg_rhs_vjp rel L2 {err:.2e}", file=sys.stderr, flush=True)
     assert err <= 1e-11
+    dm.close()
+
+
+def test_channel_2m_p4_boundaries_full_size():
+    # a channel at the headline's size class: 1000 x 1000 x 2 = 2,000,000
+    # jittered triangles (0.2h, seed 4), prescribed state on the left,
+    # outflow on the right, walls at the bottom and top, smooth flow, p=4
+    # (the matrix-core kernel's boundary variants, every stage): dg_rhs and
+    # one dg_advance step (step length fused into the stages) against the
+    # oracle, FP64 within 1e-11 and the step length within 1e-14, the mixed
+    # step within 1e-5
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+
+    WALL, OUT, STATE = W.BC_WALL, W.BC_OUTFLOW, W.BC_STATE
+    u_far = W.primitive_to_conserved(np.array(1.2), np.array(0.4), np.array(-0.1), np.array(1.1)).reshape(4)
+
+    def flow(x, y):
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+        u = 0.3 + 0.1 * np.cos(2 * np.pi * y)
+        v = -0.2 + 0.1 * np.sin(2 * np.pi * x)
+        p = 1.0 + 0.1 * np.cos(2 * np.pi * (x + y))
+        return W.primitive_to_conserved(rho, u, v, p)
+
+    p = 4
+    m = W.box_mesh(1000, 1000, 1.0, 1.0, 0.2, 4, bc=(STATE, OUT, WALL, WALL))
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    O.set_threads(min(cores, 16))
+    orc = O.Oracle(m, p)
+    orc.set_bc_state(u_far)
+    C0 = orc.project(flow)
+    dm = B.DGMesh.from_mesh(m, p)
+    dm.set_boundary_state(u_far)
+    assert dm.kernel_choice() == (16, 16)
+    case(f"channel dg_rhs + dg_advance x1 p={p} N={m.n_elem}")
+    Cg = dm.pack(torch.from_numpy(C0).cuda())
+    R = dm.unpack(dm.rhs(Cg)).cpu().numpy()
+    err = rel_l2(R, orc.rhs(C0))
+    print(f"channel p={p} dg_rhs rel L2 {err:.2e}", file=sys.stderr, flush=True)
+    assert err <= 1e-11
+    del R
+    cfl = 0.3 / (2 * p + 1)
+    dto, rc = orc.max_dt(C0, cfl)
+    assert rc == 0
+    ref = orc.rk3_step(C0, dto)
+    for prec, tol in ((B.DG_FP64, 1e-11), (B.DG_MIXED, 1e-5)):
+        A = Cg.clone()
+        hist = torch.empty(1, dtype=torch.float64, device=A.device)
+        dm.advance(A, 1, cfl, dt_hist=hist, prec=prec)
+        got = dm.unpack(A).cpu().numpy()
+        torch.cuda.synchronize()
+        dtg = float(hist.cpu()[0])
+        err = rel_l2(got, ref)
+        print(f"channel p={p} prec={prec} dg_advance step rel L2 {err:.2e}, dt {dtg:.17g} vs {dto:.17g}",
+              file=sys.stderr, flush=True)
+        assert abs(dtg - dto) <= 1e-14 * dto
+        assert err <= tol
+        del A, got
     dm.close()
