@@ -23,8 +23,7 @@ while the right-hand side of an element is their difference across it,
 which shrinks with the element; on this mesh (median inradius 1.7e-4, the
 thinnest triangles 1.6e-7) the measured error is 3.2e-5, 4.5e-5, 6.6e-5,
 6.6e-5 and 9.7e-5 of the right-hand side's L2 norm at p = 1..5 (growing
-with the order, as the lift's larger high-mode entries amplify the same
-rounding), and the state after a step still differs from the oracle's by
+with the order), and the state after a step still differs from the oracle's by
 3-4e-11.
 """
 import os
