@@ -11,7 +11,8 @@ benchmark times (step length from the per-block minima, fused into the stage
 kernels), FP64 within 1e-11 relative L2 of the oracle and the step length
 within 1e-14; the mixed form's step within 1e-5 (its stated bound for
 states); and the increment of one step ten times the CFL step.  At p = 3
-also the adjoint of the right-hand side (the matrix-core adjoint kernel).
+and 4 also the adjoint of the right-hand side (the matrix-core adjoint
+kernel).
 
 Also a channel of the same size class with all three boundary kinds
 (2,000,000 triangles, p = 4: the matrix-core kernel's boundary variants).
@@ -128,15 +129,16 @@ def test_headline_rhs_and_fused_step(mesh, p):
     dm.close()
 
 
-def test_headline_adjoint_p3(mesh):
+@pytest.mark.parametrize("p", [3, 4])
+def test_headline_adjoint(mesh, p):
     # the adjoint the benchmark times at this point (the matrix-core kernel at
-    # p=3): dg_rhs_vjp of the whole state against the oracle's hand-written
-    # adjoint (serial, about ten seconds here), 1e-11
+    # p=3, also the automatic choice at p=4): dg_rhs_vjp of the whole state
+    # against the oracle's hand-written adjoint (serial, ten to twenty seconds
+    # here), 1e-11
     import torch
 
     from paper_1601_07944_amd import binding as B
 
-    p = 3
     orc = O.Oracle(mesh, p)
     C0 = orc.project(W.density_jump)
     Rb = np.random.default_rng(11).normal(size=C0.shape)
