@@ -10,8 +10,9 @@ step's result to a new state), then chain the step adjoints backwards.  Memory: 
 every = 0 keeps every step's input and stage states from the forward pass
 itself (3N states, e.g. 192 GB for 50 steps of the 4,000,000-triangle mesh
 at p = 3): the backward pass then runs the step adjoints alone, with no
-recomputation.  choose_every() picks that when the states fit in the free
-device memory.
+recomputation.  Its steps are the out-of-place ones of the recomputation
+(dg_rk_step_stages_to), so its C_N equals dg_rk_step's to rounding.
+choose_every() picks that when the states fit in the free device memory.
 All arithmetic runs in libdgmi's kernels; torch provides memory and streams.
 """
 from __future__ import annotations
