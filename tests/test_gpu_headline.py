@@ -14,8 +14,10 @@ states); and the increment of one step ten times the CFL step.  At p = 3
 and 4 also the adjoint of the right-hand side (the matrix-core adjoint
 kernel).
 
-Also a channel of the same size class with all three boundary kinds
-(2,000,000 triangles, p = 4: the matrix-core kernel's boundary variants).
+At p = 1 also one step with the Barth-Jespersen limiter after every stage
+(the limiter workload the benchmark times).  And a channel of the same size
+class with all three boundary kinds (2,000,000 triangles, p = 4: the
+matrix-core kernel's boundary variants).
 
 The mixed form's right-hand side is held to 1e-4 here (2e-4 at p = 5), not
 to the 3e-5 of the 1,800-element meshes of the mixed-precision tests: its
@@ -210,4 +212,38 @@ def test_channel_2m_p4_boundaries_full_size():
         assert abs(dtg - dto) <= 1e-14 * dto
         assert err <= tol
         del A, got
+    dm.close()
+
+
+def test_headline_limited_step_p1(mesh):
+    # the limiter workload the benchmark times at this size (p=1, the
+    # Barth-Jespersen limiter after every stage, CFL 0.1): one dg_advance
+    # step against the oracle's limited SSP-RK3 step, FP64 within 1e-11,
+    # the step length within 1e-14; the limiter changes the step
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+
+    p = 1
+    orc = O.Oracle(mesh, p)
+    C0 = orc.project(W.density_jump)
+    dto, rc = orc.max_dt(C0, 0.1)
+    assert rc == 0
+    ref = orc.rk3_step(C0, dto, limit=True)
+    dm = B.DGMesh.from_mesh(mesh, p)
+    dm.set_limiter(dm.LIMITER_BJ)
+    case(f"headline limited dg_advance x1 p={p} N={mesh.n_elem}")
+    A = dm.pack(torch.from_numpy(C0).cuda())
+    hist = torch.empty(1, dtype=torch.float64, device=A.device)
+    dm.advance(A, 1, 0.1, dt_hist=hist)
+    got = dm.unpack(A).cpu().numpy()
+    torch.cuda.synchronize()
+    dtg = float(hist.cpu()[0])
+    err = rel_l2(got, ref)
+    effect = rel_l2(orc.rk3_step(C0, dto), ref)
+    print(f"headline limited step rel L2 {err:.2e}, dt {dtg:.17g} vs {dto:.17g}, limiter effect {effect:.1e}",
+          file=sys.stderr, flush=True)
+    assert abs(dtg - dto) <= 1e-14 * dto
+    assert err <= 1e-11
+    assert effect > 1e-9
     dm.close()
