@@ -44,7 +44,9 @@ Prints ONE JSON line.  Extra objects:
                  p = 2 and 4, 100 steps;
   cache_resident the 32,768-triangle isentropic vortex at p = 3 (state
                  10.5 MB, inside the 256 MB last-level cache), with the
-                 other surface organisations and the limiter at p = 1.
+                 other surface organisations and the limiter at p = 1;
+  boundary_mesh  a 2,000,000-triangle channel (inflow, outflow, walls) at
+                 p = 4: the automatic choice against the vector-ALU kernel.
 """
 from __future__ import annotations
 
@@ -612,6 +614,50 @@ def counter_pass(args):
                       "stage_source_sha256_16": stage_source_digest()}), flush=True)
 
 
+def boundary_mesh(steps, dev):
+    """A channel with every boundary kind: 1000 x 1000 x 2 = 2,000,000
+    jittered triangles (0.2h, seed 4) on the unit square, prescribed state on
+    the left, outflow on the right, walls at the bottom and top, smooth flow,
+    p = 4: the stage launch time of the automatic choice (the matrix-core
+    kernel's boundary variants) against the vector-ALU kernel, FP64 and
+    mixed."""
+    import numpy as np
+    import torch
+
+    from paper_1601_07944_amd import binding as B
+    from paper_1601_07944_amd import workloads as W
+
+    def flow(x, y):
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+        u = 0.3 + 0.1 * np.cos(2 * np.pi * y)
+        v = -0.2 + 0.1 * np.sin(2 * np.pi * x)
+        p = 1.0 + 0.1 * np.cos(2 * np.pi * (x + y))
+        return W.primitive_to_conserved(rho, u, v, p)
+
+    p = 4
+    mesh = W.box_mesh(1000, 1000, 1.0, 1.0, 0.2, 4, bc=(W.BC_STATE, W.BC_OUTFLOW, W.BC_WALL, W.BC_WALL))
+    dm = B.DGMesh.from_mesh(mesh, p)
+    dm.set_boundary_state(W.primitive_to_conserved(np.array(1.2), np.array(0.4), np.array(-0.1),
+                                                   np.array(1.1)).reshape(4))
+    C0 = make_state(dm, flow, dev)
+    res = {"workload": "channel, 2,000,000 jittered triangles, inflow / outflow / walls, smooth flow",
+           "n_elem": dm.n, "p": p, "steps": steps}
+    for prec, name in ((B.DG_FP64, "fp64"), (B.DG_MIXED, "mixed")):
+        row = {}
+        for label, mx in (("automatic", None), ("vector_alu", False)):
+            dm.set_matrix_cores(mx)
+            r, _ = advance_throughput(dm, C0, p, prec, steps, 3)
+            row[label] = {"kernel": stage_kernel_name(dm, p, prec), "stage_launch_us": r["stage_launch_us"],
+                          "ms_per_step": r["ms_per_step"]}
+        dm.set_matrix_cores(None)
+        row["speedup"] = row["vector_alu"]["stage_launch_us"] / row["automatic"]["stage_launch_us"]
+        res[name] = row
+    dm.close()
+    del C0, dm
+    torch.cuda.empty_cache()
+    return res
+
+
 def section(out, name, fn):
     """Runs one extra measurement; a Python error there is recorded in its
     place instead of losing the whole line."""
@@ -751,6 +797,7 @@ def main():
         section(out, "adjoint_131072", lambda: adjoint_131072(dev))
         section(out, "mixed_workload", lambda: mixed_workload(100, dev))
         section(out, "cache_resident", lambda: cache_resident(min(args.steps, 50), dev))
+        section(out, "boundary_mesh", lambda: boundary_mesh(20, dev))
     print(json.dumps(out), flush=True)
 
 
