@@ -686,6 +686,8 @@ def main():
                     help="counter pass: also --steps step adjoints (SSP-RK3, stage states stored)")
     ap.add_argument("--counter-workload", choices=["target", "cache_resident"], default="target")
     ap.add_argument("--p", default="3", help="orders of the counter pass (comma-separated)")
+    ap.add_argument("--only", choices=["boundary_mesh"],
+                    help="run only this extra measurement (for profiling it) and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X; a multi-GPU run "
@@ -703,6 +705,9 @@ def main():
     B.load()  # raises if the HIP library is not built
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only == "boundary_mesh":
+        print(json.dumps({"boundary_mesh": boundary_mesh(min(args.steps, 20), dev)}), flush=True)
+        return
     if args.counter_pass:
         counter_pass(args)
         return
